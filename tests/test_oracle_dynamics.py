@@ -1,0 +1,155 @@
+"""Pins for the oracle's time integration: velocity Verlet (energy conservation, time
+reversibility, momentum), the Langevin thermostat (equipartition, exact zero-mean noise, the
+Ornstein-Uhlenbeck closed forms for free particles) and the stress window with rotation."""
+import numpy as np
+import pytest
+
+from conftest import unvoigt
+from oracle import core
+from synth import configs
+
+
+@pytest.fixture(scope="module")
+def relaxed_kg():
+    c1 = configs.kg_single()
+    ob = core.OracleBatch(c1["params"], c1["cells"])
+    ob.run(1500)
+    st = ob.get_state(0)
+    return c1["params"], dict(x=st["x"], v=st["v"], bonds=c1["cells"][0]["bonds"], H0=st["H"])
+
+
+def test_nve_energy_drift(relaxed_kg):
+    p, cell = relaxed_kg
+    ob = core.OracleBatch(dict(p, gamma=0.0), [cell])
+    E = []
+    for _ in range(100):
+        ob.run(10)
+        pe, ke = ob.get_energy()
+        E.append(float(pe[0] + ke[0]))
+    n = len(cell["x"])
+    drift = (np.mean(E[-20:]) - np.mean(E[:20])) / n
+    assert abs(drift) < 1e-4          # per atom over 1000 steps, epsilon units
+    assert np.ptp(E) / n < 5e-3       # bounded fluctuation of the Verlet shadow energy
+
+
+def test_time_reversibility_and_momentum(relaxed_kg):
+    p, cell = relaxed_kg
+    pn = dict(p, gamma=0.0)
+    ob = core.OracleBatch(pn, [cell])
+    st0 = ob.get_state(0)
+    p0 = st0["v"].sum(0)
+    ob.run(100)
+    st = ob.get_state(0)
+    assert np.abs(st["v"].sum(0) - p0).max() < 1e-11
+    # negate velocities, keep the forces of the last step, run back
+    f = ob.get_forces(0)
+    ob2 = core.OracleBatch(pn, [dict(cell, x=st["x"], v=-st["v"], H0=st["H"])])
+    assert np.abs(ob2.get_forces(0) - f).max() < 1e-9 * np.abs(f).max()
+    ob2.run(100)
+    back = ob2.get_state(0)
+    d = back["x"] - st0["x"]
+    S = np.linalg.solve(st0["H"], d.T).T
+    d = (S - np.rint(S)) @ st0["H"].T
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(back["v"] + st0["v"]).max() < 1e-9
+
+
+def test_langevin_equipartition_and_zero_momentum(relaxed_kg):
+    p, cell = relaxed_kg
+    ob = core.OracleBatch(p, [cell])
+    n = len(cell["x"])
+    T = []
+    for _ in range(60):
+        ob.run(10)
+        T.append(2 * ob.get_energy()[1][0] / (3 * n - 3))
+        st = ob.get_state(0)
+        assert np.abs(st["v"].sum(0)).max() < 1e-9      # noise mean removed exactly per cell
+    blocks = np.array(T).reshape(6, 10).mean(1)
+    se = blocks.std(ddof=1) / np.sqrt(len(blocks))
+    assert abs(np.mean(T) - p["temperature"]) < max(3 * se, 0.02)
+
+
+def test_free_particle_ornstein_uhlenbeck():
+    # No interactions: velocity Verlet + Langevin is a discretised OU process with
+    # <v^2> -> kB T / m and velocity autocorrelation exp(-gamma t).
+    rng = np.random.default_rng(0)
+    n, L = 3000, 60.0
+    p = configs.kg_params(lj_eps=0.0, gamma=0.5, temperature=1.0, rc=1.0, skin=0.3)
+    x = rng.uniform(0, L, (n, 3))
+    ob = core.OracleBatch(p, [dict(x=x, v=np.zeros_like(x), bonds=np.zeros((0, 2), np.int32),
+                                   H0=np.eye(3) * L)])
+    ob.run(2000)                                     # t = 10 = 5 relaxation times
+    ob.get_stress()
+    ob.run(400)
+    # ideal gas: the window-averaged stress is -rho kB T on the diagonal (tension positive)
+    s = ob.get_stress()[0]
+    assert np.allclose(s[:3], -n / L ** 3 * 1.0, rtol=0.05)
+    assert np.abs(s[3:]).max() < 0.05 * n / L ** 3
+    v0 = ob.get_state(0)["v"]
+    v2 = (v0 ** 2).mean()
+    assert v2 == pytest.approx(1.0, abs=0.05)
+    k = 200                                          # t = 1
+    ob.run(k)
+    v1 = ob.get_state(0)["v"]
+    c = (v0 * v1).mean() / v2
+    assert c == pytest.approx(np.exp(-0.5 * k * p["dt"]), abs=0.03)
+
+
+def test_noise_is_keyed_by_seed_cell_step():
+    rng = np.random.default_rng(1)
+    n, L = 50, 20.0
+    p = configs.kg_params(lj_eps=0.0, gamma=1.0, temperature=1.0, rc=1.0, skin=0.3)
+    x = rng.uniform(0, L, (n, 3))
+    cell = dict(x=x, v=np.zeros_like(x), bonds=np.zeros((0, 2), np.int32), H0=np.eye(3) * L)
+    a = core.OracleBatch(p, [cell, cell])
+    a.run(3)
+    va0, va1 = a.get_state(0)["v"], a.get_state(1)["v"]
+    assert not np.array_equal(va0, va1)                     # different cell index, different noise
+    b = core.OracleBatch(p, [cell])
+    b.run(3)
+    assert np.array_equal(b.get_state(0)["v"], va0)         # batch invariance of the noise
+    c = core.OracleBatch(dict(p, seed=p["seed"] + 1), [cell])
+    c.run(3)
+    assert not np.array_equal(c.get_state(0)["v"], va0)
+    d = core.OracleBatch(p, [cell])
+    d.run(1)
+    d.run(2)
+    assert np.array_equal(d.get_state(0)["v"], va0)         # run(1) + run(2) == run(3)
+
+
+def test_window_average_then_rotate(relaxed_kg):
+    # sigma_FEM of the window average equals the average of per-step rotated stresses (linear, Q fixed)
+    p, cell = relaxed_kg
+    F = np.array([[1.05, 0.02, -0.01], [0.03, 0.97, 0.02], [-0.02, 0.01, 1.01]])
+    ob = core.OracleBatch(p, [cell])
+    ob.set_deformation(F[None])
+    ob.get_stress()
+    per_step = []
+    for _ in range(5):
+        ob.run(1)
+        per_step.append(ob.get_stress()[0])
+    ob2 = core.OracleBatch(p, [cell])
+    ob2.set_deformation(F[None])
+    ob2.get_stress()
+    ob2.run(5)
+    avg, P = ob2.get_stress(with_P=True)
+    assert np.abs(avg[0] - np.mean(per_step, 0)).max() < 1e-12 * np.abs(avg).max()
+    J = np.linalg.det(F)
+    assert np.abs(P[0] @ F.T / J - unvoigt(avg[0])).max() < 1e-12 * np.abs(avg).max()
+
+
+def test_set_deformation_is_atomic_on_error():
+    c1 = configs.kg_single()
+    ob = core.OracleBatch(c1["params"], c1["cells"] * 2)
+    st_before = ob.get_state(1)
+    bad = np.stack([np.eye(3), np.diag([1.0, 1.0, -1.0])])
+    with pytest.raises(core.OracleError) as e:
+        ob.set_deformation(bad)
+    assert e.value.code == core.ERR_BAD_F
+    st_after = ob.get_state(0)
+    assert np.array_equal(st_after["H"], st_before["H"])
+    squash = np.stack([np.eye(3), np.diag([1.0, 1.0, 0.2])])    # 2.1 sigma box < 2 (rc + skin)
+    with pytest.raises(core.OracleError) as e:
+        ob.set_deformation(squash)
+    assert e.value.code == core.ERR_BOX
+    assert np.array_equal(ob.get_state(0)["x"], st_before["x"])

@@ -1,0 +1,71 @@
+"""Plants plausible mistakes in a copy of the oracle (on the CPU) and checks that its pins catch
+each one: a pinned oracle must fail when a term is dropped, a sign flipped, an index or an
+operand order changed.  Each mutant is compiled to a temporary library and the relevant pin
+file is run against it in a subprocess."""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "rcell_oracle.c")
+
+MUTANTS = [
+    ("FENE force sign", "double g = K * r / (1.0 - t);", "double g = -K * r / (1.0 - t);", "forces"),
+    ("LJ energy shift dropped", "*pe += 4.0 * e * (sr6 * sr6 - sr6) - shift;",
+     "*pe += 4.0 * e * (sr6 * sr6 - sr6);", "forces"),
+    ("EAM embedding of j replaced by i", "(rho[q->i] + rho[q->j]) * drho", "(rho[q->i] + rho[q->i]) * drho", "forces"),
+    ("virial index", "W[3 * a + b] += g * d[a] * d[b] / r;", "W[3 * a + b] += g * d[a] * d[a] / r;", "forces"),
+    ("EAM density shift dropped", "double rr = pow(a / q->r, p->sc_m) - rhoc;", "double rr = pow(a / q->r, p->sc_m);", "forces"),
+    ("rotation reversed", "mul3(Q, s, t);\n  mul3(t, Qt, sf);", "mul3(Qt, s, t);\n  mul3(t, Q, sf);", "coupling"),
+    ("F^-1 instead of F^-T", "mul3(sf, FiT, pm);", "mul3(sf, Fi, pm);", "coupling"),
+    ("Delta R operand order", "mul3(R + 9 * k, Ri, dR + 9 * k);", "mul3(Ri, R + 9 * k, dR + 9 * k);", "coupling"),
+    ("tilt reduction drops the xy part of c", "H[2] -= k * H[1]; H[5] -= k * H[4];", "H[5] -= k * H[4];", "coupling"),
+    ("Gram-Schmidt projection sign", "v[0] -= s * q[i][0]; v[1] -= s * q[i][1];", "v[0] += s * q[i][0]; v[1] -= s * q[i][1];", "coupling"),
+    ("noise variance halved", "double c24 = sqrt(24.0 *", "double c24 = sqrt(12.0 *", "dynamics"),
+    ("drag sign", "double drag = -(p->gamma", "double drag = (p->gamma", "dynamics"),
+    ("kinetic stress sign", "(W[3 * ia[k] + ib[k]] - K[3 * ia[k] + ib[k]]) / V",
+     "(W[3 * ia[k] + ib[k]] + K[3 * ia[k] + ib[k]]) / V", "dynamics"),
+    ("full kick instead of half kick", "double h = p->dt / (2.0 * p->mass * p->mvv2e);",
+     "double h = p->dt / (p->mass * p->mvv2e);", "dynamics"),
+    ("Philox Weyl constant", "k0 += 0x9E3779B9u;", "k0 += 0x9E3779B7u;", "philox"),
+]
+
+
+def _run_mutant(m, tmp):
+    name, old, new, target = m
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique or missing: {name}"
+    mdir = os.path.join(tmp, f"{abs(hash(name))}_{target}")
+    os.makedirs(mdir, exist_ok=True)
+    csrc = os.path.join(mdir, "m.c")
+    with open(csrc, "w") as fh:
+        fh.write(src.replace(old, new))
+    for h in ("rcell_oracle.h",):
+        with open(os.path.join(mdir, h), "w") as fh:
+            fh.write(open(os.path.join(ROOT, "oracle", h)).read())
+    lib = os.path.join(mdir, "libm_oracle.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", csrc, "-o", lib, "-lm"])
+    env = dict(os.environ, RCELL_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", f"test_oracle_{target}.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
+
+
+CONTROLS = [("unmutated copy", "int orc_threads(int32_t n) {", "int orc_threads(int32_t n) {", t)
+            for t in ("forces", "coupling", "dynamics", "philox")]
+
+
+def test_pins_catch_planted_mistakes():
+    with tempfile.TemporaryDirectory() as tmp:
+        with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+            results = list(ex.map(lambda m: _run_mutant(m, tmp), MUTANTS + CONTROLS))
+    controls = results[len(MUTANTS):]
+    results = results[:len(MUTANTS)]
+    assert all(rc == 0 for _, rc in controls), f"the harness fails on the unmutated oracle: {controls}"
+    survivors = [name for name, rc in results if rc == 0]
+    assert not survivors, f"mutants not caught by the pins: {survivors}"
