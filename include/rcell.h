@@ -1,0 +1,149 @@
+/* rcell.h — C ABI of the batched r-cell molecular-dynamics library for MI355X (gfx950).
+ *
+ * Method: Murashima, Urata & Li, "Coupling finite element method with LAMMPS for hierarchical
+ * multiscale simulations", arXiv:1902.09171.  Every finite-element quadrature point owns a
+ * periodic MD representative cell (r-cell).  The FE solver hands each cell a deformation
+ * gradient F; the cell's box follows only the upper-triangular stretch R of F = Q R (Sec. 2.1,
+ * Eqs. 4-6, 9); MD runs in that box; the time-averaged MD stress is rotated back by Q and
+ * converted to the first Piola-Kirchhoff stress (Eqs. 7-8).  This library runs many such cells
+ * batched on one GPU.
+ *
+ * Conventions for every call:
+ *  - All functions return an int status: RCELL_OK (0) or a negative RCELL_ERR_* code.  No C++
+ *    exception crosses the ABI.  rcell_last_error() gives a human-readable message.
+ *  - Host pointers are read (or written) during the call only; the library copies every input.
+ *    Pointers named *_dev are device pointers owned by the caller, used on the context's stream.
+ *  - Matrices are 3x3 row-major doubles.  F_ij = dx_i / dX_j.  A box matrix H has the cell edge
+ *    vectors as its columns, so r = H S for scaled coordinates S in [0,1)^3 (Eq. 1).
+ *  - 6-component stresses are Voigt-ordered xx, yy, zz, xy, xz, yz, Cauchy, tension positive,
+ *    in the potential's native units (LJ: epsilon/sigma^3; metal units: eV/Angstrom^3).
+ *  - A context is used from one host thread at a time; several contexts may coexist.
+ *  - Work is enqueued on the context's HIP stream.  rcell_run only enqueues; errors raised on the
+ *    device during a run are reported by the next call that synchronises (get_* calls).
+ */
+#ifndef RCELL_H
+#define RCELL_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RCELL_OK = 0,
+  RCELL_ERR_ARG = -1,        /* invalid argument, null pointer, unknown option */
+  RCELL_ERR_BAD_F = -2,      /* F non-finite, det F <= 0, or some R_ii < 1e-12 |F|_F */
+  RCELL_ERR_BOX = -3,        /* a perpendicular cell width w satisfies w/2 < rc + skin */
+  RCELL_ERR_BOND = -4,       /* a FENE bond reached r >= R0 */
+  RCELL_ERR_NONFINITE = -5,  /* a returned stress is not finite */
+  RCELL_ERR_OOM = -6,        /* device or host allocation failed */
+  RCELL_ERR_DEVICE = -7,     /* a HIP runtime call failed */
+  RCELL_ERR_STATE = -8       /* invalid state (bad box in set_state, neighbour capacity exceeded) */
+};
+enum { RCELL_POT_KG = 1, RCELL_POT_SC_EAM = 2 };
+enum { RCELL_PREC_FP64 = 0, RCELL_PREC_MIXED = 1 };
+
+typedef struct {
+  int32_t potential;       /* RCELL_POT_KG: Kremer-Grest bead-spring (Sec. 3.2); RCELL_POT_SC_EAM:
+                              Sutton-Chen embedded atom (stand-in for the copper EAM of Sec. 3.1) */
+  int32_t precision;       /* RCELL_PREC_MIXED: FP32 pair forces, FP64 positions, velocities,
+                              integration and stress; RCELL_PREC_FP64: everything in FP64 */
+  double dt;               /* time step */
+  double temperature;      /* Langevin target temperature */
+  double gamma;            /* Langevin friction rate (1/time); 0 gives plain velocity Verlet */
+  double mass;             /* particle mass */
+  double kB;               /* Boltzmann constant in energy units per temperature unit */
+  double mvv2e;            /* energy of mass*velocity^2 (1 in LJ units; 103.64269656 eV per
+                              amu*A^2/fs^2 in metal units with fs) */
+  double rc;               /* interaction cutoff */
+  double skin;             /* neighbour-list skin; the list is rebuilt when an atom of the cell
+                              has moved more than skin/2 since the last build */
+  double lj_eps, lj_sigma; /* KG: LJ truncated at rc and shifted to zero there (WCA at 2^(1/6)) */
+  double fene_K, fene_R0;  /* KG: FENE bonds U = -K R0^2/2 ln(1 - (r/R0)^2) */
+  double sc_eps, sc_a, sc_c; /* Sutton-Chen: E = sum_i [1/2 sum_j eps phi(r_ij) - eps c sqrt(rho_i)] */
+  int32_t sc_n, sc_m;      /* phi = (a/r)^n - (a/rc)^n, rho_i = sum_j (a/r)^m - (a/rc)^m */
+  uint64_t seed;           /* Philox4x32-10 key = (low, high 32 bits of seed) */
+  int32_t include_kinetic; /* 1: sigma includes -sum m v (x) v / V (thermal r-cells) */
+} rcell_params;
+
+typedef struct {           /* one cell, host arrays copied at create */
+  int32_t natoms;          /* >= 1 */
+  int32_t nbonds;          /* number of FENE bonds (KG), 0 otherwise */
+  const double* H0;        /* 9, upper triangular with positive diagonal: initial box H(0) */
+  const double* x;         /* natoms*3 positions (any periodic image; wrapped into the box) */
+  const double* v;         /* natoms*3 velocities, or NULL for zero */
+  const int32_t* bonds;    /* nbonds*2 atom indices within the cell, or NULL; at most 4 bonds per atom */
+} rcell_cell_init;
+
+typedef struct rcell_ctx rcell_ctx;
+
+/* Create a batch of ncells r-cells on the current HIP device.  hip_stream: a hipStream_t to
+ * enqueue on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a library-owned
+ * stream.  Validates the boxes (RCELL_ERR_BOX), bond lengths (RCELL_ERR_BOND) and indices, then
+ * computes the initial forces and the instantaneous stress.  Before any rcell_set_deformation
+ * the cells have F = Q = R = I.  On failure *out is NULL. */
+int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32_t ncells,
+                 void* hip_stream, rcell_ctx** out);
+
+/* Eqs. (4), (5), (9) of Sec. 2.1: per cell, F = Q R by Gram-Schmidt with R_ii > 0; the box is
+ * updated incrementally by Delta R = R R_prev^-1 (H <- Delta R H, kept within half-tilt bounds by
+ * lattice-preserving basis changes) and every position is mapped by Delta R (affine remap,
+ * velocities unchanged); then R_prev <- R, forces are recomputed (conservative part only) and
+ * the stress window is cleared.  F: ncells*9 host doubles.  Every cell is validated before any
+ * state changes: on RCELL_ERR_BAD_F or RCELL_ERR_BOX no cell is modified.  Synchronises. */
+int rcell_set_deformation(rcell_ctx* ctx, const double* F);
+
+/* As rcell_set_deformation, with F (ncells*9 doubles) in device memory. */
+int rcell_set_deformation_dev(rcell_ctx* ctx, const void* F_dev);
+
+/* Advance every cell by nsteps velocity-Verlet steps with the Langevin thermostat; after each
+ * step the MD stress sigma_MD = (W - sum m v (x) v)/V (pair virial W of Eq. 15) is added to the
+ * cell's averaging window.  Only enqueues; device-side errors (FENE bond r >= R0, neighbour
+ * capacity) set the cell's status and are returned by the next synchronising call. */
+int rcell_run(rcell_ctx* ctx, int32_t nsteps);
+
+/* Window average of sigma_MD since the last get_stress / set_deformation (or the instantaneous
+ * stress if the window is empty), rotated to the FE frame sigma_FEM = Q sigma Q^T (Eq. 7), and
+ * the first Piola-Kirchhoff stress P = J sigma_FEM F^-T (Eq. 8).  sigma: ncells*6 host doubles;
+ * P: ncells*9 host doubles or NULL.  Clears the window.  Synchronises; returns the first
+ * per-cell error status if any (RCELL_ERR_NONFINITE for a non-finite stress). */
+int rcell_get_stress(rcell_ctx* ctx, double* sigma, double* P);
+
+/* As rcell_get_stress, writing ncells*6 (and ncells*9, if P_dev is not NULL) doubles to
+ * caller-owned device memory, enqueued on the context's stream; does not synchronise. */
+int rcell_get_stress_dev(rcell_ctx* ctx, void* sigma_dev, void* P_dev);
+
+/* Free every device and host resource of the context.  Always safe, also on NULL. */
+int rcell_destroy(rcell_ctx* ctx);
+
+/* Message of the last error on this context (or of the last failed create when ctx is NULL). */
+const char* rcell_last_error(const rcell_ctx* ctx);
+
+/* ---- diagnostics, checkpointing and test hooks (all synchronise) ---- */
+/* per-cell status codes (0 or RCELL_ERR_*), ncells int32 */
+int rcell_get_status(rcell_ctx* ctx, int32_t* status);
+/* total force of the last completed step (or the conservative force after create /
+ * set_deformation / set_state), natoms*3 doubles, original atom order */
+int rcell_get_forces(rcell_ctx* ctx, int32_t cell, double* f);
+/* state of one cell: x, v natoms*3; H 9; Rprev 9; step.  Any pointer may be NULL. */
+int rcell_get_state(rcell_ctx* ctx, int32_t cell, double* x, double* v, double* H, double* Rprev,
+                    int64_t* step);
+/* overwrite the state of one cell (checkpoint restore); recomputes its forces and clears its
+ * window.  H must be upper triangular with w/2 >= rc + skin (else RCELL_ERR_STATE / _BOX). */
+int rcell_set_state(rcell_ctx* ctx, int32_t cell, const double* x, const double* v, const double* H,
+                    const double* Rprev, int64_t step);
+/* potential energy of the last force evaluation and kinetic energy 1/2 sum m v^2, ncells each */
+int rcell_get_energy(rcell_ctx* ctx, double* pe, double* ke);
+/* box H, rotation Q, stretch R (9 each) and J = det F of one cell; any pointer may be NULL */
+int rcell_get_box(rcell_ctx* ctx, int32_t cell, double* H, double* Q, double* R, double* J);
+/* neighbour-list rebuilds performed so far, summed over cells */
+int rcell_get_rebuilds(rcell_ctx* ctx, int64_t* count);
+/* choose the lanes-per-atom of the force kernels: 0 = autotune by timing each variant on the
+ * current state (advances no state), or 1, 2, 4, 8, 16 */
+int rcell_set_lanes(rcell_ctx* ctx, int32_t lanes);
+int rcell_get_lanes(rcell_ctx* ctx, int32_t* lanes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1021 @@
+// Device side of the batched r-cell MD library (gfx950).
+//
+// Data layout (one batch = all cells of a context, atoms of cell c at [off_c, off_c + n_c)):
+//   x, y, z     FP64 SoA master positions        vx, vy, vz  FP64 SoA velocities
+//   fx, fy, fz  FP64 total force of the last completed step (read by the first kick of a run)
+//   s[2]        double-buffered fixed-point scaled coordinates: S = frac(H^-1 x) * 2^32 (int32,
+//               mixed) or * 2^64 (int64, FP64 mode); .w carries F'(rho) for the EAM force pass.
+//               Differences of two such integers wrap modulo 2^32 (2^64), which is exactly the
+//               per-component minimum image in scaled space: the pair separation needs no
+//               image shifts and no FP64 arithmetic (d = H dS, H as a float hi + lo pair).
+//   sb          s at the last neighbour build (displacement check)
+//   nbr         Verlet list within rc + skin, column-major nbr[k * npad + i], cell-local j
+//   bond        up to four FENE partners per atom (cell-local, -1 = none)
+// Work is distributed over 64-atom tiles (a tile never straddles two cells); each tile writes
+// one partial record and a per-cell kernel reduces them in a fixed order (deterministic).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcell {
+
+constexpr int TILE = 64;
+constexpr double TWO32 = 4294967296.0;
+constexpr double TWOM32 = 1.0 / 4294967296.0;
+
+enum Mode : int { MODE_PRIME = 0, MODE_STEP = 1, MODE_LAST = 2, MODE_DRY = 3 };
+enum RedMode : int { RED_START = 0, RED_PRIME = 1, RED_STEP = 2, RED_LAST = 3 };
+enum Status : int { ST_OK = 0, ST_BOND = -4, ST_CAP = -8, ST_BOX = -3, ST_BAD_F = -2 };
+
+struct alignas(32) S64 { long long x, y, z, w; };
+
+struct CellDev {
+  double H[9], Hi[9];             // box (upper triangular) and its inverse
+  double Rprev[9], Q[9], R[9], F[9];
+  double J, V;
+  double xi_mean[3];              // per-cell mean of the integer noise for the next time level
+  double wsum[6], last[6];        // stress window sum and last sample (Voigt, tension +)
+  double pe;
+  double Hd[6];                   // H * 2^-64, upper triangle (FP64 mode)
+  float Hhi[6], Hlo[6];           // H * 2^-32 as float hi + lo (mixed mode)
+  long long wcount, step, nrebuild;
+  int off, n, tile_off, ntile;
+  int nb[3], bin_off, bin_cap;
+  int rebuild, pending, status, pad;
+};
+
+struct Tile { int cell, begin, count, pad; };
+
+struct Part {                     // one tile's contribution
+  double W[6], K[6], pe, pad;
+  long long xi[3];
+  float maxd2;
+  int status;
+};
+
+struct Stage {                    // set_deformation staging, one per cell
+  double Q[9], R[9], dR[9], Hn[9], F[9];
+  double J, wmin;
+  int nb[3], nbins, status;
+  double density;
+};
+
+struct MDArgs {
+  double *x, *y, *z, *vx, *vy, *vz;
+  void *fx, *fy, *fz;
+  void *s_cur, *s_nxt, *sb;
+  const int4* bond;
+  int* nn;
+  int* nbr;
+  long long npad;
+  int maxnb;
+  CellDev* cells;
+  const Tile* tiles;
+  Part* parts;
+  int ntiles, ncells;
+  int* abin; int* bcount; int* bstart; int* bnum; int* bfill; int* binned;
+  // integrator constants (computed once on the host, documented expressions)
+  double dt, h, drag, c24, mmv, half_skin2, rcs2;
+  uint32_t key0, key1;
+  int gamma_on, include_kinetic, pot;
+  // pair constants
+  double rc2, lj_eps, lj_sig2, lj_shift, fene_K, fene_R02, sc_eps, sc_a, sc_c, sc_phic, sc_rhoc;
+  int sc_n, sc_m;
+};
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror & Shaw (SC'11): 10 rounds of two 32x32->64 multiplies with the published
+// multipliers; the key is bumped by the published Weyl increments between rounds.
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// integer noise units k = (w >> 8) - 2^23 for the three components of atom gid of cell at level step
+__device__ __forceinline__ void noise_units(const MDArgs& a, int gid, int cell, long long step, int k[3]) {
+  uint32_t w[4];
+  philox((uint32_t)gid, (uint32_t)cell, (uint32_t)(unsigned long long)step,
+         (uint32_t)((unsigned long long)step >> 32), a.key0, a.key1, w);
+  k[0] = (int)(w[0] >> 8) - (1 << 23);
+  k[1] = (int)(w[1] >> 8) - (1 << 23);
+  k[2] = (int)(w[2] >> 8) - (1 << 23);
+}
+
+// ------------------------------------------------------------------ precision policies
+struct Mixed {
+  using S = int4;
+  using R = float;
+  using Fst = double;   // stored total force: touched once per run, kept in FP64 so runs split bitwise
+  __device__ static S load(const void* p, long long i) { return ((const int4*)p)[i]; }
+  __device__ static void store_xyz(void* p, long long i, const S& v) { ((int4*)p)[i] = v; }
+  __device__ static void store_w(void* p, long long i, R fp) { ((int4*)p)[i].w = __float_as_int(fp); }
+  __device__ static R get_w(const S& v) { return __int_as_float(v.w); }
+  // scaled fraction f in [0,1) -> 32-bit fixed point (2^32 wraps to 0)
+  __device__ static int fix1(double f) {
+    return (int)(unsigned int)(unsigned long long)(long long)rint(f * TWO32);
+  }
+  __device__ static S make(double f0, double f1, double f2) { return make_int4(fix1(f0), fix1(f1), fix1(f2), 0); }
+  __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) {
+    const float a = (float)(int)((unsigned)sj.x - (unsigned)si.x);
+    const float b = (float)(int)((unsigned)sj.y - (unsigned)si.y);
+    const float c = (float)(int)((unsigned)sj.z - (unsigned)si.z);
+    // H (upper triangular: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz) applied as hi + lo float pair
+    d[0] = fmaf(C.Hhi[0], a, fmaf(C.Hhi[1], b, C.Hhi[2] * c)) + fmaf(C.Hlo[0], a, fmaf(C.Hlo[1], b, C.Hlo[2] * c));
+    d[1] = fmaf(C.Hhi[3], b, C.Hhi[4] * c) + fmaf(C.Hlo[3], b, C.Hlo[4] * c);
+    d[2] = C.Hhi[5] * c + C.Hlo[5] * c;
+  }
+};
+
+struct FP64 {
+  using S = S64;
+  using R = double;
+  using Fst = double;
+  __device__ static S load(const void* p, long long i) { return ((const S64*)p)[i]; }
+  __device__ static void store_xyz(void* p, long long i, const S& v) { ((S64*)p)[i] = v; }
+  __device__ static void store_w(void* p, long long i, R fp) { ((S64*)p)[i].w = __double_as_longlong(fp); }
+  __device__ static R get_w(const S& v) { return __longlong_as_double(v.w); }
+  // scaled fraction f in [0,1) -> 64-bit fixed point, rounded to nearest, 2^64 wraps to 0
+  __device__ static long long fix1(double f) {
+    const double t = f * TWO32;
+    const double hi = floor(t);
+    const double lo = rint((t - hi) * TWO32);
+    const unsigned long long u = ((unsigned long long)(unsigned int)(long long)hi << 32) + (unsigned long long)(long long)lo;
+    return (long long)u;
+  }
+  __device__ static S make(double f0, double f1, double f2) { S s; s.x = fix1(f0); s.y = fix1(f1); s.z = fix1(f2); s.w = 0; return s; }
+  __device__ static double cvt(long long v) {       // signed 64-bit integer to double, rounded
+    return (double)v;
+  }
+  __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) {
+    const double a = cvt((long long)((unsigned long long)sj.x - (unsigned long long)si.x));
+    const double b = cvt((long long)((unsigned long long)sj.y - (unsigned long long)si.y));
+    const double c = cvt((long long)((unsigned long long)sj.z - (unsigned long long)si.z));
+    d[0] = C.Hd[0] * a + C.Hd[1] * b + C.Hd[2] * c;
+    d[1] = C.Hd[3] * b + C.Hd[4] * c;
+    d[2] = C.Hd[5] * c;
+  }
+};
+
+// S = H^-1 x for upper-triangular H^-1, reduced to its fractional part
+__device__ __forceinline__ void scaled_frac(const CellDev& C, double x, double y, double z, double f[3]) {
+  const double s0 = C.Hi[0] * x + C.Hi[1] * y + C.Hi[2] * z;
+  const double s1 = C.Hi[4] * y + C.Hi[5] * z;
+  const double s2 = C.Hi[8] * z;
+  f[0] = s0 - floor(s0);
+  f[1] = s1 - floor(s1);
+  f[2] = s2 - floor(s2);
+}
+
+template <class P>
+__device__ __forceinline__ typename P::S fixed_pos(const CellDev& C, double x, double y, double z) {
+  double f[3];
+  scaled_frac(C, x, y, z, f);
+  return P::make(f[0], f[1], f[2]);
+}
+
+template <class T>
+__device__ __forceinline__ T ipow(T t, int n) {
+  T r = (T)1;
+  while (n) {
+    if (n & 1) r *= t;
+    t *= t;
+    n >>= 1;
+  }
+  return r;
+}
+
+// ------------------------------------------------------------------ block reductions
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // fixed-shape tree: deterministic for a given block size
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const long long r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = fmaxf(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const float r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ int block_min_i(int v, int* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = min(sh[t], sh[t + s]);
+    __syncthreads();
+  }
+  const int r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// reduce a value across the TPA consecutive lanes that share one atom (result in every lane)
+template <int TPA, class T>
+__device__ __forceinline__ T lane_sum(T v) {
+#pragma unroll
+  for (int o = TPA / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TPA);
+  return v;
+}
+
+// ------------------------------------------------------------------ per-atom integration tail
+// Completes the time level of atom i after its conservative force fc is known:
+//   Langevin (drag + noise with the per-cell mean removed), second half kick (v_full), the
+//   kinetic stress term, and in MODE_STEP the next first half kick and drift with the new
+//   fixed-point position, displacement check and the next level's noise sums.
+struct TailOut {
+  double K[6];
+  float maxd2;
+  long long xi[3];
+};
+
+template <class P>
+__device__ __forceinline__ void atom_tail(const MDArgs& a, const CellDev& C, int cell, long long i,
+                                          double fcx, double fcy, double fcz, int mode, TailOut& o) {
+  double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+  const int gid = (int)(i - C.off);
+  double f0 = fcx, f1 = fcy, f2 = fcz;
+  if (mode == MODE_PRIME) {
+    // forces after create / deformation / restore: conservative part only; v is a full-step velocity
+    ((typename P::Fst*)a.fx)[i] = (typename P::Fst)f0;
+    ((typename P::Fst*)a.fy)[i] = (typename P::Fst)f1;
+    ((typename P::Fst*)a.fz)[i] = (typename P::Fst)f2;
+  } else {
+    if (a.gamma_on) {
+      int k[3];
+      noise_units(a, gid, cell, C.step + 1, k);
+      f0 = (f0 + a.drag * vx) + a.c24 * ((double)k[0] - C.xi_mean[0]);
+      f1 = (f1 + a.drag * vy) + a.c24 * ((double)k[1] - C.xi_mean[1]);
+      f2 = (f2 + a.drag * vz) + a.c24 * ((double)k[2] - C.xi_mean[2]);
+    }
+    vx += a.h * f0;  // v(t + dt) from the half-step velocity
+    vy += a.h * f1;
+    vz += a.h * f2;
+  }
+  o.K[0] = a.mmv * vx * vx; o.K[1] = a.mmv * vy * vy; o.K[2] = a.mmv * vz * vz;
+  o.K[3] = a.mmv * vx * vy; o.K[4] = a.mmv * vx * vz; o.K[5] = a.mmv * vy * vz;
+  o.maxd2 = 0.f;
+  o.xi[0] = o.xi[1] = o.xi[2] = 0;
+  if (mode == MODE_LAST) {
+    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+    ((typename P::Fst*)a.fx)[i] = (typename P::Fst)f0;
+    ((typename P::Fst*)a.fy)[i] = (typename P::Fst)f1;
+    ((typename P::Fst*)a.fz)[i] = (typename P::Fst)f2;
+  } else if (mode == MODE_STEP) {
+    vx += a.h * f0;  // first half kick of the next step
+    vy += a.h * f1;
+    vz += a.h * f2;
+    const double x = a.x[i] + a.dt * vx, y = a.y[i] + a.dt * vy, z = a.z[i] + a.dt * vz;
+    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+    a.x[i] = x; a.y[i] = y; a.z[i] = z;
+    const typename P::S sn = fixed_pos<P>(C, x, y, z);
+    P::store_xyz(a.s_nxt, i, sn);
+    typename P::R d[3];
+    P::sep(sn, P::load(a.sb, i), C, d);
+    o.maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (a.gamma_on) {
+      int k[3];
+      noise_units(a, gid, cell, C.step + 2, k);
+      o.xi[0] = k[0]; o.xi[1] = k[1]; o.xi[2] = k[2];
+    }
+  }
+}
+
+// sum over the 64 lanes of a wave by xor shuffles (fixed pattern: deterministic)
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int NW>
+struct PartShared {
+  double d[NW][13];
+  long long l[NW][3];
+  float f[NW];
+  int i[NW];
+};
+
+// Reduce one tile's contributions (every thread of the block calls this) and write its Part:
+// a wave-level shuffle reduction, then thread 0 adds the NW wave results in order.
+template <int NT>
+__device__ __forceinline__ void write_part(Part* parts, const double W[6], const double K[6], double pe,
+                                           const long long xi[3], float maxd2, int status,
+                                           PartShared<NT / 64>& sh) {
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  double r[13];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) { r[q] = wave_sum(W[q]); r[6 + q] = wave_sum(K[q]); }
+  r[12] = wave_sum(pe);
+  const long long x0 = wave_sum(xi[0]), x1 = wave_sum(xi[1]), x2 = wave_sum(xi[2]);
+  const float m = wave_max(maxd2);
+  const int st = wave_min(status);
+  if (ln == 0) {
+#pragma unroll
+    for (int q = 0; q < 13; ++q) sh.d[wv][q] = r[q];
+    sh.l[wv][0] = x0; sh.l[wv][1] = x1; sh.l[wv][2] = x2;
+    sh.f[wv] = m;
+    sh.i[wv] = st;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Part& p = parts[blockIdx.x];
+    double acc[13];
+    long long la[3] = {0, 0, 0};
+    float mm = 0.f;
+    int ss = 0;
+#pragma unroll
+    for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+#pragma unroll
+      for (int q = 0; q < 13; ++q) acc[q] += sh.d[w][q];
+      la[0] += sh.l[w][0]; la[1] += sh.l[w][1]; la[2] += sh.l[w][2];
+      mm = fmaxf(mm, sh.f[w]);
+      ss = min(ss, sh.i[w]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { p.W[q] = acc[q]; p.K[q] = acc[6 + q]; }
+    p.pe = acc[12];
+    p.xi[0] = la[0]; p.xi[1] = la[1]; p.xi[2] = la[2];
+    p.maxd2 = mm;
+    p.status = ss;
+  }
+}
+
+// ------------------------------------------------------------------ force kernels
+// Kremer-Grest: LJ truncated and shifted at rc on every listed pair + FENE on bonds; then the
+// integration tail.  TPA lanes share one atom's neighbour list.
+template <class P, int TPA>
+__global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
+  using R = typename P::R;
+  constexpr int NT = TILE * TPA;
+  __shared__ PartShared<NT / 64> psh;
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
+  const bool skip = (mode == MODE_PRIME && !C.pending);
+  const bool active = slot < t.count && !skip;
+  const long long i = (long long)t.begin + slot;
+  R f[3] = {0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
+  int status = 0;
+  if (active) {
+    const typename P::S si = P::load(a.s_cur, i);
+    const int nn = a.nn[i];
+    const R rc2 = (R)a.rc2, sig2 = (R)a.lj_sig2, e24 = (R)(24.0 * a.lj_eps), e4 = (R)(4.0 * a.lj_eps), sh = (R)a.lj_shift;
+    for (int k = lane; k < nn; k += TPA) {
+      const int j = a.nbr[(long long)k * a.npad + i] + C.off;
+      R d[3];
+      P::sep(P::load(a.s_cur, j), si, C, d);
+      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (r2 < rc2) {
+        const R r2i = (R)1 / r2;
+        const R s2 = sig2 * r2i;
+        const R s6 = s2 * s2 * s2;
+        const R gr = -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i;   // (dU/dr) / r
+        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+        const R hg = (R)0.5 * gr;
+        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+        pe += (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh);
+      }
+    }
+    if (lane == 0) {
+      const int4 b = a.bond[i];
+      const int bp[4] = {b.x, b.y, b.z, b.w};
+      const R K = (R)a.fene_K, R02 = (R)a.fene_R02;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (bp[q] < 0) continue;
+        R d[3];
+        P::sep(P::load(a.s_cur, bp[q] + C.off), si, C, d);
+        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const R tt = r2 / R02;
+        if (!(tt < (R)1)) { status = ST_BOND; continue; }
+        const R gr = K / ((R)1 - tt);
+        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+        const R hg = (R)0.5 * gr;
+        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+        pe += (R)(-0.25 * a.fene_K * a.fene_R02) * (R)log((double)((R)1 - tt));
+      }
+    }
+  }
+  double W[6], K[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) W[q] = (double)lane_sum<TPA>(w[q]);
+  double PE = (double)lane_sum<TPA>(pe);
+  const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
+  long long xi[3] = {0, 0, 0};
+  float maxd2 = 0.f;
+  if (lane != 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) W[q] = 0.0;
+    PE = 0.0;
+  }
+  if (active && lane == 0 && mode != MODE_DRY) {
+    TailOut o;
+    atom_tail<P>(a, C, t.cell, i, fc0, fc1, fc2, mode, o);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) K[q] = o.K[q];
+    xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
+    maxd2 = o.maxd2;
+  }
+  write_part<NT>(a.parts, W, K, PE, xi, maxd2, status, psh);
+}
+
+// Sutton-Chen pass 1: host density rho_i and F'(rho_i) = -eps c / (2 sqrt(rho_i)), stored in s.w
+template <class P, int TPA>
+__global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
+  using R = typename P::R;
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
+  const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending);
+  const long long i = (long long)t.begin + slot;
+  R rho = 0;
+  if (active) {
+    const typename P::S si = P::load(a.s_cur, i);
+    const int nn = a.nn[i];
+    const R rc2 = (R)a.rc2, sa = (R)a.sc_a, rhoc = (R)a.sc_rhoc;
+    for (int k = lane; k < nn; k += TPA) {
+      const int j = a.nbr[(long long)k * a.npad + i] + C.off;
+      R d[3];
+      P::sep(P::load(a.s_cur, j), si, C, d);
+      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (r2 < rc2) {
+        const R tr = sa * ((R)1 / sqrt(r2));
+        rho += ipow(tr, a.sc_m) - rhoc;
+      }
+    }
+  }
+  rho = lane_sum<TPA>(rho);
+  if (active && lane == 0) {
+    const R fp = rho > (R)0 ? (R)(-0.5 * a.sc_eps * a.sc_c) / sqrt(rho) : (R)0;
+    P::store_w(a.s_cur, i, fp);
+  }
+}
+
+// Sutton-Chen pass 2: pair scalar g = eps phi'(r) + (F'_i + F'_j) rho'(r), then the tail
+template <class P, int TPA>
+__global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
+  using R = typename P::R;
+  constexpr int NT = TILE * TPA;
+  __shared__ PartShared<NT / 64> psh;
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
+  const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending);
+  const long long i = (long long)t.begin + slot;
+  R f[3] = {0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
+  R fpi = 0;
+  if (active) {
+    const typename P::S si = P::load(a.s_cur, i);
+    fpi = P::get_w(si);
+    const int nn = a.nn[i];
+    const R rc2 = (R)a.rc2, sa = (R)a.sc_a, en = (R)(a.sc_eps * a.sc_n), m = (R)a.sc_m;
+    const R eh = (R)(0.5 * a.sc_eps), phic = (R)a.sc_phic;
+    for (int k = lane; k < nn; k += TPA) {
+      const int j = a.nbr[(long long)k * a.npad + i] + C.off;
+      const typename P::S sj = P::load(a.s_cur, j);
+      R d[3];
+      P::sep(sj, si, C, d);
+      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (r2 < rc2) {
+        const R ri = (R)1 / sqrt(r2);
+        const R tr = sa * ri;
+        const R tm = ipow(tr, a.sc_m);
+        const R tn = ipow(tr, a.sc_n);
+        const R gr = -(ri * ri) * (en * tn + (fpi + P::get_w(sj)) * m * tm);   // g / r
+        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+        const R hg = (R)0.5 * gr;
+        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+        pe += eh * (tn - phic);
+      }
+    }
+  }
+  double W[6], K[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) W[q] = (double)lane_sum<TPA>(w[q]);
+  double PE = (double)lane_sum<TPA>(pe);
+  const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
+  long long xi[3] = {0, 0, 0};
+  float maxd2 = 0.f;
+  if (lane != 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) W[q] = 0.0;
+    PE = 0.0;
+  } else if (active) {
+    // embedding energy -eps c sqrt(rho) = (eps c)^2 / (2 F'(rho)), zero where rho = 0
+    const double ec = a.sc_eps * a.sc_c;
+    if (fpi != (R)0) PE += ec * ec / (2.0 * (double)fpi);
+  }
+  if (active && lane == 0 && mode != MODE_DRY) {
+    TailOut o;
+    atom_tail<P>(a, C, t.cell, i, fc0, fc1, fc2, mode, o);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) K[q] = o.K[q];
+    xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
+    maxd2 = o.maxd2;
+  }
+  write_part<NT>(a.parts, W, K, PE, xi, maxd2, 0, psh);
+}
+
+// First half kick and drift of a run (the remaining ones are fused into the force kernels).
+template <class P>
+__global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
+  __shared__ PartShared<1> psh;
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  const long long i = (long long)t.begin + threadIdx.x;
+  long long xi[3] = {0, 0, 0};
+  float maxd2 = 0.f;
+  if ((int)threadIdx.x < t.count) {
+    const double f0 = (double)((const typename P::Fst*)a.fx)[i];
+    const double f1 = (double)((const typename P::Fst*)a.fy)[i];
+    const double f2 = (double)((const typename P::Fst*)a.fz)[i];
+    const double vx = a.vx[i] + a.h * f0, vy = a.vy[i] + a.h * f1, vz = a.vz[i] + a.h * f2;
+    const double x = a.x[i] + a.dt * vx, y = a.y[i] + a.dt * vy, z = a.z[i] + a.dt * vz;
+    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+    a.x[i] = x; a.y[i] = y; a.z[i] = z;
+    const typename P::S sn = fixed_pos<P>(C, x, y, z);
+    P::store_xyz(a.s_cur, i, sn);
+    typename P::R d[3];
+    P::sep(sn, P::load(a.sb, i), C, d);
+    maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (a.gamma_on) {
+      int k[3];
+      noise_units(a, (int)(i - C.off), t.cell, C.step + 1, k);
+      xi[0] = k[0]; xi[1] = k[1]; xi[2] = k[2];
+    }
+  }
+  const double Z[6] = {0, 0, 0, 0, 0, 0};
+  write_part<TILE>(a.parts, Z, Z, 0.0, xi, maxd2, 0, psh);
+}
+
+// Per-cell reduction of the tile partials (one 256-thread block per cell, fixed order).
+constexpr int RED_NT = 256;
+__global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
+  __shared__ double shd[RED_NT];
+  __shared__ long long shl[RED_NT];
+  __shared__ float shf[RED_NT];
+  __shared__ int shi[RED_NT];
+  CellDev& C = a.cells[blockIdx.x];
+  if (mode == RED_PRIME && !C.pending) return;
+  double W[6] = {0, 0, 0, 0, 0, 0}, K[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
+  long long xi[3] = {0, 0, 0};
+  float m = 0.f;
+  int st = 0;
+  for (int k = threadIdx.x; k < C.ntile; k += RED_NT) {
+    const Part& p = a.parts[C.tile_off + k];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { W[q] += p.W[q]; K[q] += p.K[q]; }
+    pe += p.pe;
+    xi[0] += p.xi[0]; xi[1] += p.xi[1]; xi[2] += p.xi[2];
+    m = fmaxf(m, p.maxd2);
+    st = min(st, p.status);
+  }
+  double r[13];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) r[q] = block_sum<RED_NT>(W[q], shd);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) r[6 + q] = block_sum<RED_NT>(K[q], shd);
+  r[12] = block_sum<RED_NT>(pe, shd);
+  const long long x0 = block_sum_ll<RED_NT>(xi[0], shl), x1 = block_sum_ll<RED_NT>(xi[1], shl),
+                  x2 = block_sum_ll<RED_NT>(xi[2], shl);
+  const float md = block_max<RED_NT>(m, shf);
+  st = block_min_i<RED_NT>(st, shi);
+  if (threadIdx.x != 0) return;
+  if (st != 0 && C.status == 0) C.status = st;
+  if (C.rebuild) C.nrebuild += 1;
+  if (mode == RED_START) {
+    C.rebuild = md > (float)a.half_skin2;
+    C.xi_mean[0] = (double)x0 / (double)C.n;
+    C.xi_mean[1] = (double)x1 / (double)C.n;
+    C.xi_mean[2] = (double)x2 / (double)C.n;
+    return;
+  }
+  double s[6];
+  const double kin = a.include_kinetic ? 1.0 : 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) s[q] = (r[q] - kin * r[6 + q]) / C.V;
+  C.pe = r[12];
+  if (mode == RED_PRIME) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) C.last[q] = s[q];
+    C.rebuild = 0;
+    C.pending = 0;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) { C.wsum[q] += s[q]; C.last[q] = s[q]; }
+  C.wcount += 1;
+  C.step += 1;
+  if (mode == RED_STEP) {
+    C.rebuild = md > (float)a.half_skin2;
+    C.xi_mean[0] = (double)x0 / (double)C.n;
+    C.xi_mean[1] = (double)x1 / (double)C.n;
+    C.xi_mean[2] = (double)x2 / (double)C.n;
+  } else {
+    C.rebuild = 0;
+  }
+}
+
+// ------------------------------------------------------------------ neighbour build
+// 1: wrap positions into the box, fixed-point S, bin in scaled space, histogram per cell
+template <class P>
+__global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  const long long i = (long long)t.begin + threadIdx.x;
+  double x = a.x[i], y = a.y[i], z = a.z[i];
+  const double s0 = C.Hi[0] * x + C.Hi[1] * y + C.Hi[2] * z, s1 = C.Hi[4] * y + C.Hi[5] * z, s2 = C.Hi[8] * z;
+  const double k0 = floor(s0), k1 = floor(s1), k2 = floor(s2);
+  if (k0 != 0.0 || k1 != 0.0 || k2 != 0.0) {      // x -= H k (lattice vector), H upper triangular
+    x -= C.H[0] * k0 + C.H[1] * k1 + C.H[2] * k2;
+    y -= C.H[4] * k1 + C.H[5] * k2;
+    z -= C.H[8] * k2;
+    a.x[i] = x; a.y[i] = y; a.z[i] = z;
+  }
+  double f[3];
+  scaled_frac(C, x, y, z, f);
+  typename P::S s = P::make(f[0], f[1], f[2]);
+  P::store_xyz(a.s_cur, i, s);
+  P::store_xyz(a.sb, i, s);
+  int b[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) b[q] = min((int)(f[q] * C.nb[q]), C.nb[q] - 1);
+  const int bin = (b[0] * C.nb[1] + b[1]) * C.nb[2] + b[2];
+  a.abin[i] = bin;
+  atomicAdd(&a.bcount[C.bin_off + bin], 1);
+}
+
+// 2: exclusive scan of the bin histogram (one block per cell)
+constexpr int SCAN_NT = 256;
+__global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
+  __shared__ int sh[SCAN_NT];
+  const CellDev& C = a.cells[blockIdx.x];
+  if (!C.rebuild) return;
+  const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
+  const int per = (nbins + SCAN_NT - 1) / SCAN_NT;
+  const int lo = min(nbins, (int)threadIdx.x * per), hi = min(nbins, lo + per);
+  int s = 0;
+  for (int b = lo; b < hi; ++b) s += a.bcount[C.bin_off + b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < SCAN_NT; ++q) { const int v = sh[q]; sh[q] = acc; acc += v; }
+  }
+  __syncthreads();
+  int acc = sh[threadIdx.x];
+  for (int b = lo; b < hi; ++b) {
+    const int c = a.bcount[C.bin_off + b];
+    a.bstart[C.bin_off + b] = acc;
+    a.bnum[C.bin_off + b] = c;
+    a.bcount[C.bin_off + b] = 0;
+    a.bfill[C.bin_off + b] = 0;
+    acc += c;
+  }
+}
+
+// 3: scatter cell-local atom indices into their bins
+__global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  const long long i = (long long)t.begin + threadIdx.x;
+  const int bin = a.abin[i];
+  const int slot = atomicAdd(&a.bfill[C.bin_off + bin], 1);
+  a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
+}
+
+// 4: order each bin by atom index, so that neighbour lists (and force sums) are deterministic
+__global__ __launch_bounds__(SCAN_NT) void k_bin_sort(MDArgs a) {
+  const CellDev& C = a.cells[blockIdx.x];
+  if (!C.rebuild) return;
+  const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
+  for (int b = threadIdx.x; b < nbins; b += SCAN_NT) {
+    int* p = a.binned + C.off + a.bstart[C.bin_off + b];
+    const int n = a.bnum[C.bin_off + b];
+    for (int u = 1; u < n; ++u) {
+      const int v = p[u];
+      int q = u - 1;
+      while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
+      p[q + 1] = v;
+    }
+  }
+}
+
+// 5: Verlet list of every atom: cell-local j with |d| < rc + skin over the 27 (distinct) bins
+template <class P>
+__global__ __launch_bounds__(TILE) void k_build_list(MDArgs a) {
+  const Tile t = a.tiles[blockIdx.x];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  const long long i = (long long)t.begin + threadIdx.x;
+  const int li = (int)(i - C.off);
+  const typename P::S si = P::load(a.s_cur, i);
+  const int bin = a.abin[i];
+  const int b2 = bin % C.nb[2], b1 = (bin / C.nb[2]) % C.nb[1], b0 = bin / (C.nb[2] * C.nb[1]);
+  int lst[3][3], cnt[3];
+  const int bb[3] = {b0, b1, b2};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int nbq = C.nb[q];
+    if (nbq >= 3) {
+      cnt[q] = 3;
+      lst[q][0] = (bb[q] + nbq - 1) % nbq; lst[q][1] = bb[q]; lst[q][2] = (bb[q] + 1) % nbq;
+    } else {
+      cnt[q] = nbq;
+      for (int u = 0; u < nbq; ++u) lst[q][u] = u;
+    }
+  }
+  const typename P::R rcs2 = (typename P::R)a.rcs2;
+  int n = 0;
+  for (int u0 = 0; u0 < cnt[0]; ++u0)
+    for (int u1 = 0; u1 < cnt[1]; ++u1)
+      for (int u2 = 0; u2 < cnt[2]; ++u2) {
+        const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
+        const int* p = a.binned + C.off + a.bstart[C.bin_off + b];
+        const int m = a.bnum[C.bin_off + b];
+        for (int q = 0; q < m; ++q) {
+          const int lj = p[q];
+          if (lj == li) continue;
+          typename P::R d[3];
+          P::sep(P::load(a.s_cur, C.off + lj), si, C, d);
+          if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
+            if (n < a.maxnb) a.nbr[(long long)n * a.npad + i] = lj;
+            ++n;
+          }
+        }
+      }
+  if (n > a.maxnb) {
+    atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
+    n = a.maxnb;
+  }
+  a.nn[i] = n;
+}
+
+// ------------------------------------------------------------------ QR box remap (Eqs. 4, 5, 9)
+__device__ inline double det3(const double A[9]) {
+  return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+__device__ inline void mat3mul(const double A[9], const double B[9], double C[9]) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) C[3 * r + c] = A[3 * r] * B[c] + A[3 * r + 1] * B[3 + c] + A[3 * r + 2] * B[6 + c];
+}
+__device__ inline void upper_inv(const double U[9], double Ui[9]) {   // inverse of an upper-triangular matrix
+  const double a = U[0], b = U[1], c = U[2], d = U[4], e = U[5], f = U[8];
+  Ui[0] = 1.0 / a; Ui[1] = -b / (a * d); Ui[2] = (b * e - c * d) / (a * d * f);
+  Ui[3] = 0.0; Ui[4] = 1.0 / d; Ui[5] = -e / (d * f);
+  Ui[6] = 0.0; Ui[7] = 0.0; Ui[8] = 1.0 / f;
+}
+__device__ inline void box_widths(const double H[9], double w[3]) {  // w_k = V / |a_i x a_j| for columns of H
+  const double V = fabs(det3(H));
+  for (int k = 0; k < 3; ++k) {
+    const int i = (k + 1) % 3, j = (k + 2) % 3;
+    const double u0 = H[i], u1 = H[3 + i], u2 = H[6 + i], v0 = H[j], v1 = H[3 + j], v2 = H[6 + j];
+    const double cx = u1 * v2 - u2 * v1, cy = u2 * v0 - u0 * v2, cz = u0 * v1 - u1 * v0;
+    w[k] = V / sqrt(cx * cx + cy * cy + cz * cz);
+  }
+}
+
+// F = Q R by classical Gram-Schmidt on the columns of F with one re-orthogonalisation pass;
+// R_jj = |v_j| > 0.  Returns 0 or ST_BAD_F (non-finite F, det F <= 0, R_jj < 1e-12 |F|_F).
+__device__ inline int qr_gs(const double F[9], double Q[9], double R[9]) {
+  double fn = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    if (!isfinite(F[k])) return ST_BAD_F;
+    fn += F[k] * F[k];
+    R[k] = 0.0;
+  }
+  fn = sqrt(fn);
+  if (!(det3(F) > 0.0)) return ST_BAD_F;
+  double q[3][3];
+  for (int j = 0; j < 3; ++j) {
+    double v0 = F[j], v1 = F[3 + j], v2 = F[6 + j];
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i < j; ++i) {
+        const double s = q[i][0] * v0 + q[i][1] * v1 + q[i][2] * v2;
+        R[3 * i + j] += s;
+        v0 -= s * q[i][0]; v1 -= s * q[i][1]; v2 -= s * q[i][2];
+      }
+    const double nv = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    if (!(nv >= 1e-12 * fn)) return ST_BAD_F;
+    R[3 * j + j] = nv;
+    q[j][0] = v0 / nv; q[j][1] = v1 / nv; q[j][2] = v2 / nv;
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Q[3 * r + c] = q[c][r];
+  return 0;
+}
+
+// keep |yz| <= ly/2, |xz| <= lx/2, |xy| <= lx/2 by subtracting integer multiples of box edges
+__device__ inline void tilt_reduce(double H[9]) {
+  if (fabs(H[5]) > 0.5 * H[4]) { const double k = floor(H[5] / H[4] + 0.5); H[2] -= k * H[1]; H[5] -= k * H[4]; }
+  if (fabs(H[2]) > 0.5 * H[0]) { const double k = floor(H[2] / H[0] + 0.5); H[2] -= k * H[0]; }
+  if (fabs(H[1]) > 0.5 * H[0]) { const double k = floor(H[1] / H[0] + 0.5); H[1] -= k * H[0]; }
+}
+
+// stage everything a deformation needs; no state is modified
+__global__ void k_qr_stage(const double* Fall, const CellDev* cells, Stage* st, int ncells, double rcs) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  Stage& S = st[c];
+  const CellDev& C = cells[c];
+  for (int k = 0; k < 9; ++k) S.F[k] = Fall[9 * c + k];
+  S.status = qr_gs(S.F, S.Q, S.R);
+  if (S.status) return;
+  double Ri[9];
+  upper_inv(C.Rprev, Ri);
+  mat3mul(S.R, Ri, S.dR);                       // Eq. (9)
+  S.dR[3] = S.dR[6] = S.dR[7] = 0.0;
+  mat3mul(S.dR, C.H, S.Hn);                     // H <- Delta R H
+  S.Hn[3] = S.Hn[6] = S.Hn[7] = 0.0;
+  tilt_reduce(S.Hn);
+  S.J = S.R[0] * S.R[4] * S.R[8];
+  double w[3];
+  box_widths(S.Hn, w);
+  S.wmin = fmin(w[0], fmin(w[1], w[2]));
+  if (rcs > 0.5 * S.wmin) { S.status = ST_BOX; return; }
+  for (int q = 0; q < 3; ++q) S.nb[q] = max(1, (int)floor(w[q] / rcs));
+  S.nbins = S.nb[0] * S.nb[1] * S.nb[2];
+  S.density = (double)C.n / fabs(det3(S.Hn));
+}
+
+// fill the derived box fields of a cell from C.H
+__device__ inline void set_box_fields(CellDev& C, double rcs) {
+  upper_inv(C.H, C.Hi);
+  C.V = det3(C.H);
+  const int up[6] = {0, 1, 2, 4, 5, 8};
+  for (int q = 0; q < 6; ++q) {
+    const double hs = C.H[up[q]] * TWOM32;
+    const float hi = (float)hs;
+    C.Hhi[q] = hi;
+    C.Hlo[q] = (float)(hs - (double)hi);
+    C.Hd[q] = hs * TWOM32;
+  }
+  double w[3];
+  box_widths(C.H, w);
+  for (int q = 0; q < 3; ++q) C.nb[q] = max(1, (int)floor(w[q] / rcs));
+  // never exceed the bins allocated to this cell: coarser bins are still valid (>= rc + skin)
+  while (C.nb[0] * C.nb[1] * C.nb[2] > max(C.bin_cap, 1)) {
+    int q = 0;
+    if (C.nb[1] > C.nb[q]) q = 1;
+    if (C.nb[2] > C.nb[q]) q = 2;
+    C.nb[q] -= 1;
+  }
+}
+
+__global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double rcs) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  CellDev& C = cells[c];
+  const Stage& S = st[c];
+  for (int k = 0; k < 9; ++k) {
+    C.H[k] = S.Hn[k]; C.Q[k] = S.Q[k]; C.R[k] = S.R[k]; C.Rprev[k] = S.R[k]; C.F[k] = S.F[k];
+  }
+  C.J = S.J;
+  set_box_fields(C, rcs);
+  for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
+  C.wcount = 0;
+  C.rebuild = 1;
+  C.pending = 1;
+}
+
+// x <- Delta R x for every atom (affine remap, Eq. 6 applied incrementally)
+__global__ __launch_bounds__(TILE) void k_remap(MDArgs a, const Stage* st) {
+  const Tile t = a.tiles[blockIdx.x];
+  if ((int)threadIdx.x >= t.count) return;
+  const double* d = st[t.cell].dR;
+  const long long i = (long long)t.begin + threadIdx.x;
+  const double x = a.x[i], y = a.y[i], z = a.z[i];
+  a.x[i] = d[0] * x + d[1] * y + d[2] * z;
+  a.y[i] = d[4] * y + d[5] * z;
+  a.z[i] = d[8] * z;
+}
+
+// set a cell's box from H (create / set_state) and request a rebuild + prime
+__global__ void k_set_box(CellDev* cells, int first, int count, double rcs) {
+  const int c = first + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= first + count) return;
+  CellDev& C = cells[c];
+  set_box_fields(C, rcs);
+  for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
+  C.wcount = 0;
+  C.rebuild = 1;
+  C.pending = 1;
+}
+
+// ------------------------------------------------------------------ stress return (Eqs. 7, 8)
+__global__ void k_stress_out(CellDev* cells, int ncells, double* sig, double* P) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  CellDev& C = cells[c];
+  double sv[6];
+  for (int q = 0; q < 6; ++q) sv[q] = C.wcount > 0 ? C.wsum[q] / (double)C.wcount : C.last[q];
+  const double s[9] = {sv[0], sv[3], sv[4], sv[3], sv[1], sv[5], sv[4], sv[5], sv[2]};
+  double Qt[9], T[9], Sf[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) Qt[3 * r + k] = C.Q[3 * k + r];
+  mat3mul(C.Q, s, T);
+  mat3mul(T, Qt, Sf);                              // sigma_FEM = Q sigma_MD Q^T
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  bool finite = true;
+  for (int q = 0; q < 6; ++q) {
+    sig[6 * c + q] = Sf[3 * ia[q] + ib[q]];
+    finite = finite && isfinite(Sf[3 * ia[q] + ib[q]]);
+  }
+  if (!finite && C.status == 0) C.status = -5;
+  if (P) {
+    const double* F = C.F;
+    const double d = det3(F);
+    // F^-T: transpose of the adjugate over det
+    double FiT[9];
+    FiT[0] = (F[4] * F[8] - F[5] * F[7]) / d; FiT[3] = (F[2] * F[7] - F[1] * F[8]) / d; FiT[6] = (F[1] * F[5] - F[2] * F[4]) / d;
+    FiT[1] = (F[5] * F[6] - F[3] * F[8]) / d; FiT[4] = (F[0] * F[8] - F[2] * F[6]) / d; FiT[7] = (F[2] * F[3] - F[0] * F[5]) / d;
+    FiT[2] = (F[3] * F[7] - F[4] * F[6]) / d; FiT[5] = (F[1] * F[6] - F[0] * F[7]) / d; FiT[8] = (F[0] * F[4] - F[1] * F[3]) / d;
+    double Pm[9];
+    mat3mul(Sf, FiT, Pm);                          // P = J sigma_FEM F^-T
+    for (int q = 0; q < 9; ++q) P[9 * c + q] = C.J * Pm[q];
+  }
+  for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
+  C.wcount = 0;
+}
+
+// kinetic energy 1/2 sum m v^2 per cell (one block per cell, fixed order)
+__global__ __launch_bounds__(RED_NT) void k_kinetic(MDArgs a, double* ke) {
+  __shared__ double shd[RED_NT];
+  const CellDev& C = a.cells[blockIdx.x];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < C.n; k += RED_NT) {
+    const long long i = (long long)C.off + k;
+    s += a.vx[i] * a.vx[i] + a.vy[i] * a.vy[i] + a.vz[i] * a.vz[i];
+  }
+  s = block_sum<RED_NT>(s, shd);
+  if (threadIdx.x == 0) ke[blockIdx.x] = 0.5 * a.mmv * s;
+}
+
+__global__ void k_set_pending(CellDev* cells, int first, int count) {
+  const int c = first + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < first + count) { cells[c].rebuild = 1; cells[c].pending = 1; }
+}
+
+}  // namespace rcell

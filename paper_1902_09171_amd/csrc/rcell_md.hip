@@ -1,0 +1,712 @@
+// Host side of the batched r-cell MD C ABI (include/rcell.h): context lifetime, memory layout,
+// argument marshalling (AoS <-> SoA), and the launch sequence of every call.  All arithmetic of
+// the method runs in the kernels of md_device.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rcell.h"
+#include "md_device.h"
+
+using namespace rcell;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct rcell_ctx {
+  rcell_params p{};
+  bool fp64 = false;
+  int ncells = 0;
+  long long N = 0, npad = 0;
+  int ntiles = 0;
+  int maxnb = 0;
+  int lanes = 1;
+  int cur = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::vector<int> off, n, tile_off, ntile, bin_off, bin_cap;
+  long long bins_total = 0;
+  // device memory
+  double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
+  void *fx = nullptr, *fy = nullptr, *fz = nullptr;
+  void *s[2] = {nullptr, nullptr}, *sb = nullptr;
+  int4* bond = nullptr;
+  int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr;
+  int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
+  CellDev* cells = nullptr;
+  Tile* tiles = nullptr;
+  Part* parts = nullptr;
+  Stage* stage = nullptr;
+  double* dscratch = nullptr;     // ncells * 17 doubles: F / sigma + P / kinetic, then pe
+  int* iscratch = nullptr;        // ncells ints
+  long long* lscratch = nullptr;  // ncells long longs
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int fail(rcell_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail((ctx), RCELL_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+int dalloc(rcell_ctx* c, T** out, size_t count) {
+  void* p = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, RCELL_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(p);
+  *out = (T*)p;
+  return RCELL_OK;
+}
+
+void dfree(rcell_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+double width_min(const double H[9]) {   // host-side validation of a box against rc + skin
+  auto col = [&](int k, double v[3]) { v[0] = H[k]; v[1] = H[3 + k]; v[2] = H[6 + k]; };
+  double a[3][3];
+  for (int k = 0; k < 3; ++k) col(k, a[k]);
+  const double V = std::fabs(a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                             a[1][0] * (a[0][1] * a[2][2] - a[0][2] * a[2][1]) +
+                             a[2][0] * (a[0][1] * a[1][2] - a[0][2] * a[1][1]));
+  double w = 1e300;
+  for (int k = 0; k < 3; ++k) {
+    const double* u = a[(k + 1) % 3];
+    const double* v = a[(k + 2) % 3];
+    const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+    w = std::min(w, V / std::sqrt(cx * cx + cy * cy + cz * cz));
+  }
+  return w;
+}
+
+int bins_for(const double H[9], double rcs) {
+  // an upper bound on floor(w0/rcs) floor(w1/rcs) floor(w2/rcs): V / rcs^3
+  const double V = H[0] * H[4] * H[8];
+  return std::max(1, (int)std::floor(V / (rcs * rcs * rcs)));
+}
+
+int list_capacity(double density, double rcs) {
+  const double expect = density * 4.0 / 3.0 * M_PI * rcs * rcs * rcs;
+  return (int)std::ceil(1.6 * expect + 24.0);
+}
+
+MDArgs make_args(const rcell_ctx* c) {
+  MDArgs a{};
+  a.x = c->x; a.y = c->y; a.z = c->z; a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
+  a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
+  a.s_cur = c->s[c->cur]; a.s_nxt = c->s[1 - c->cur]; a.sb = c->sb;
+  a.bond = c->bond; a.nn = c->nn; a.nbr = c->nbr; a.npad = c->npad; a.maxnb = c->maxnb;
+  a.cells = c->cells; a.tiles = c->tiles; a.parts = c->parts; a.ntiles = c->ntiles; a.ncells = c->ncells;
+  a.abin = c->abin; a.bcount = c->bcount; a.bstart = c->bstart; a.bnum = c->bnum; a.bfill = c->bfill;
+  a.binned = c->binned;
+  const rcell_params& p = c->p;
+  // integrator constants: the same expressions, in the same order, as the method's definition
+  a.dt = p.dt;
+  a.h = p.dt / (2.0 * p.mass * p.mvv2e);
+  a.drag = -(p.gamma * p.mass * p.mvv2e);
+  a.c24 = std::sqrt(24.0 * p.gamma * p.mass * p.kB * p.temperature * p.mvv2e / p.dt) * 0x1.0p-24;
+  a.mmv = p.mass * p.mvv2e;
+  a.half_skin2 = 0.25 * p.skin * p.skin;
+  a.rcs2 = (p.rc + p.skin) * (p.rc + p.skin);
+  a.key0 = (uint32_t)p.seed;
+  a.key1 = (uint32_t)(p.seed >> 32);
+  a.gamma_on = p.gamma > 0.0;
+  a.include_kinetic = p.include_kinetic;
+  a.pot = p.potential;
+  a.rc2 = p.rc * p.rc;
+  a.lj_eps = p.lj_eps;
+  a.lj_sig2 = p.lj_sigma * p.lj_sigma;
+  {
+    const double sr6 = std::pow(p.lj_sigma / p.rc, 6.0);
+    a.lj_shift = 4.0 * p.lj_eps * (sr6 * sr6 - sr6);
+  }
+  a.fene_K = p.fene_K;
+  a.fene_R02 = p.fene_R0 * p.fene_R0;
+  a.sc_eps = p.sc_eps; a.sc_a = p.sc_a; a.sc_c = p.sc_c;
+  a.sc_n = p.sc_n; a.sc_m = p.sc_m;
+  a.sc_phic = p.potential == RCELL_POT_SC_EAM ? std::pow(p.sc_a / p.rc, p.sc_n) : 0.0;
+  a.sc_rhoc = p.potential == RCELL_POT_SC_EAM ? std::pow(p.sc_a / p.rc, p.sc_m) : 0.0;
+  return a;
+}
+
+// ---------------------------------------------------------------- launch helpers
+template <class P, int TPA>
+void force_t(rcell_ctx* c, const MDArgs& a, int mode) {
+  const dim3 grid(c->ntiles), block(TILE * TPA);
+  if (c->p.potential == RCELL_POT_KG) {
+    hipLaunchKernelGGL((k_force_kg<P, TPA>), grid, block, 0, c->stream, a, mode);
+  } else {
+    hipLaunchKernelGGL((k_eam_rho<P, TPA>), grid, block, 0, c->stream, a, mode);
+    hipLaunchKernelGGL((k_force_eam<P, TPA>), grid, block, 0, c->stream, a, mode);
+  }
+}
+
+template <class P>
+void force_p(rcell_ctx* c, const MDArgs& a, int mode, int lanes) {
+  switch (lanes) {
+    case 2: force_t<P, 2>(c, a, mode); break;
+    case 4: force_t<P, 4>(c, a, mode); break;
+    case 8: force_t<P, 8>(c, a, mode); break;
+    case 16: force_t<P, 16>(c, a, mode); break;
+    default: force_t<P, 1>(c, a, mode); break;
+  }
+}
+
+void launch_force(rcell_ctx* c, int mode, int lanes = -1) {
+  const MDArgs a = make_args(c);
+  const int l = lanes > 0 ? lanes : c->lanes;
+  if (c->fp64) force_p<FP64>(c, a, mode, l); else force_p<Mixed>(c, a, mode, l);
+}
+
+void launch_reduce(rcell_ctx* c, int mode) {
+  const MDArgs a = make_args(c);
+  hipLaunchKernelGGL(k_reduce, dim3(c->ncells), dim3(RED_NT), 0, c->stream, a, mode);
+}
+
+void launch_build(rcell_ctx* c) {
+  const MDArgs a = make_args(c);
+  const dim3 gt(c->ntiles), bt(TILE), gc(c->ncells), bc(SCAN_NT);
+  if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gt, bt, 0, c->stream, a);
+  else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
+  hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
+  hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
+  hipLaunchKernelGGL(k_bin_sort, gc, bc, 0, c->stream, a);
+  if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gt, bt, 0, c->stream, a);
+  else hipLaunchKernelGGL(k_build_list<Mixed>, gt, bt, 0, c->stream, a);
+}
+
+void launch_start(rcell_ctx* c) {
+  const MDArgs a = make_args(c);
+  if (c->fp64) hipLaunchKernelGGL(k_start<FP64>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a);
+  else hipLaunchKernelGGL(k_start<Mixed>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a);
+}
+
+// neighbour build + conservative forces for every cell flagged pending
+int prime(rcell_ctx* c) {
+  launch_build(c);
+  launch_force(c, MODE_PRIME);
+  launch_reduce(c, RED_PRIME);
+  HIPCHK(c, hipGetLastError());
+  return RCELL_OK;
+}
+
+struct Gathered {
+  std::vector<int> status;
+  std::vector<double> pe;
+  std::vector<long long> nreb, step;
+};
+
+__global__ void k_gather(const CellDev* cells, int ncells, int* st, double* pe, long long* nreb, long long* step) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  st[c] = cells[c].status;
+  pe[c] = cells[c].pe;
+  nreb[c] = cells[c].nrebuild;
+  step[c] = cells[c].step;
+}
+
+__global__ void k_set_bins(CellDev* cells, int ncells, const int* off, const int* cap) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  cells[c].bin_off = off[c];
+  cells[c].bin_cap = cap[c];
+}
+
+int gather(rcell_ctx* c, Gathered& g) {
+  const int nc = c->ncells;
+  double* pe = c->dscratch + 16 * nc;
+  long long* nreb = c->lscratch;
+  long long* step = c->lscratch + nc;
+  hipLaunchKernelGGL(k_gather, dim3((nc + 127) / 128), dim3(128), 0, c->stream, c->cells, nc, c->iscratch, pe, nreb, step);
+  g.status.resize(nc); g.pe.resize(nc); g.nreb.resize(nc); g.step.resize(nc);
+  HIPCHK(c, hipMemcpyAsync(g.status.data(), c->iscratch, sizeof(int) * nc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(g.pe.data(), pe, sizeof(double) * nc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(g.nreb.data(), nreb, sizeof(long long) * nc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(g.step.data(), step, sizeof(long long) * nc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RCELL_OK;
+}
+
+int first_error(rcell_ctx* c, const std::vector<int>& st) {
+  for (size_t k = 0; k < st.size(); ++k)
+    if (st[k] != 0) {
+      const char* what = st[k] == RCELL_ERR_BOND ? "FENE bond reached R0" :
+                         st[k] == RCELL_ERR_STATE ? "neighbour capacity exceeded" :
+                         st[k] == RCELL_ERR_NONFINITE ? "non-finite stress" : "cell error";
+      return fail(c, st[k], std::string(what) + " in cell " + std::to_string(k));
+    }
+  return RCELL_OK;
+}
+
+// lay out bins with capacity caps (>= need), update the device cell table
+int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
+  long long total = 0;
+  std::vector<int> off(c->ncells), cap(c->ncells);
+  for (int k = 0; k < c->ncells; ++k) {
+    cap[k] = std::max(need[k], c->bin_cap.empty() ? 0 : c->bin_cap[k]);
+    off[k] = (int)total;
+    total += cap[k];
+  }
+  if (total > (1ll << 31) - 1) return fail(c, RCELL_ERR_OOM, "too many neighbour bins");
+  if (total > c->bins_total) {
+    dfree(c, c->bcount); dfree(c, c->bstart); dfree(c, c->bnum); dfree(c, c->bfill);
+    c->bcount = c->bstart = c->bnum = c->bfill = nullptr;
+    int st;
+    if ((st = dalloc(c, &c->bcount, total)) || (st = dalloc(c, &c->bstart, total)) ||
+        (st = dalloc(c, &c->bnum, total)) || (st = dalloc(c, &c->bfill, total)))
+      return st;
+    HIPCHK(c, hipMemsetAsync(c->bcount, 0, sizeof(int) * total, c->stream));
+    c->bins_total = total;
+  }
+  c->bin_off = off;
+  c->bin_cap = cap;
+  int *doff = c->iscratch, *dcap = c->iscratch + c->ncells;
+  HIPCHK(c, hipMemcpyAsync(doff, off.data(), sizeof(int) * c->ncells, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dcap, cap.data(), sizeof(int) * c->ncells, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_set_bins, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->cells, c->ncells, doff, dcap);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RCELL_OK;
+}
+
+int ensure_list_capacity(rcell_ctx* c, int need) {
+  if (need <= c->maxnb) return RCELL_OK;
+  dfree(c, c->nbr);
+  c->nbr = nullptr;
+  const int st = dalloc(c, &c->nbr, (size_t)need * c->npad);
+  if (st) return st;
+  c->maxnb = need;
+  return RCELL_OK;
+}
+
+void destroy_all(rcell_ctx* c) {
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  c->stream = nullptr;
+}
+
+int deformation_common(rcell_ctx* c, const double* F_dev) {
+  const int nc = c->ncells;
+  const double rcs = c->p.rc + c->p.skin;
+  hipLaunchKernelGGL(k_qr_stage, dim3((nc + 63) / 64), dim3(64), 0, c->stream, F_dev, c->cells, c->stage, nc, rcs);
+  std::vector<Stage> st(nc);
+  HIPCHK(c, hipMemcpyAsync(st.data(), c->stage, sizeof(Stage) * nc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < nc; ++k)
+    if (st[k].status != 0)
+      return fail(c, st[k].status, (st[k].status == RCELL_ERR_BOX ? std::string("box too small for rc + skin")
+                                                                   : std::string("bad deformation gradient")) +
+                                       " in cell " + std::to_string(k));
+  std::vector<int> need(nc);
+  double dens = 0.0;
+  bool grow = false;
+  for (int k = 0; k < nc; ++k) {
+    need[k] = st[k].nbins;
+    grow = grow || need[k] > c->bin_cap[k];
+    dens = std::max(dens, st[k].density);
+  }
+  int e;
+  if (grow && (e = layout_bins(c, need))) return e;
+  if ((e = ensure_list_capacity(c, list_capacity(dens, rcs)))) return e;
+  hipLaunchKernelGGL(k_qr_commit, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, c->stage, nc, rcs);
+  const MDArgs a = make_args(c);
+  hipLaunchKernelGGL(k_remap, dim3(c->ntiles), dim3(TILE), 0, c->stream, a, c->stage);
+  return prime(c);
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32_t ncells, void* hip_stream,
+                 rcell_ctx** out) {
+  if (!out) return fail(nullptr, RCELL_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params || !cells || ncells < 1) return fail(nullptr, RCELL_ERR_ARG, "params, cells and ncells >= 1 are required");
+  const rcell_params& p = *params;
+  if (p.potential != RCELL_POT_KG && p.potential != RCELL_POT_SC_EAM)
+    return fail(nullptr, RCELL_ERR_ARG, "unknown potential");
+  if (p.precision != RCELL_PREC_FP64 && p.precision != RCELL_PREC_MIXED)
+    return fail(nullptr, RCELL_ERR_ARG, "unknown precision");
+  if (!(p.dt > 0) || !(p.mass > 0) || !(p.mvv2e > 0) || !(p.rc > 0) || !(p.skin >= 0) || !(p.gamma >= 0) ||
+      !(p.temperature >= 0) || !(p.kB >= 0))
+    return fail(nullptr, RCELL_ERR_ARG, "dt, mass, mvv2e, rc must be > 0; skin, gamma, temperature, kB >= 0");
+  if (p.potential == RCELL_POT_KG && (!(p.lj_sigma > 0) || !(p.fene_R0 > 0)))
+    return fail(nullptr, RCELL_ERR_ARG, "KG needs lj_sigma > 0 and fene_R0 > 0");
+  if (p.potential == RCELL_POT_SC_EAM && (!(p.sc_a > 0) || p.sc_n < 1 || p.sc_m < 1))
+    return fail(nullptr, RCELL_ERR_ARG, "Sutton-Chen needs sc_a > 0 and n, m >= 1");
+  const double rcs = p.rc + p.skin;
+
+  rcell_ctx* c = new (std::nothrow) rcell_ctx();
+  if (!c) return fail(nullptr, RCELL_ERR_OOM, "host allocation failed");
+  c->p = p;
+  c->fp64 = p.precision == RCELL_PREC_FP64;
+  c->ncells = ncells;
+  c->lanes = p.potential == RCELL_POT_SC_EAM ? 8 : 1;
+  auto bail = [&](int code) {
+    g_create_error = c->err.empty() ? g_create_error : c->err;
+    destroy_all(c);
+    delete c;
+    return code;
+  };
+  // ---- host validation and layout
+  long long N = 0;
+  int ntiles = 0;
+  double dens = 0.0;
+  std::vector<int> need_bins(ncells);
+  for (int k = 0; k < ncells; ++k) {
+    const rcell_cell_init& ci = cells[k];
+    if (ci.natoms < 1 || !ci.H0 || !ci.x || ci.nbonds < 0 || (ci.nbonds > 0 && !ci.bonds))
+      return bail(fail(c, RCELL_ERR_ARG, "cell " + std::to_string(k) + ": natoms >= 1, H0 and x are required"));
+    const double* H = ci.H0;
+    if (!(H[0] > 0 && H[4] > 0 && H[8] > 0) || H[3] != 0 || H[6] != 0 || H[7] != 0)
+      return bail(fail(c, RCELL_ERR_ARG, "cell " + std::to_string(k) + ": H0 must be upper triangular with positive diagonal"));
+    if (0.5 * width_min(H) < rcs)
+      return bail(fail(c, RCELL_ERR_BOX, "cell " + std::to_string(k) + ": box too small for rc + skin"));
+    c->off.push_back((int)N);
+    c->n.push_back(ci.natoms);
+    c->tile_off.push_back(ntiles);
+    const int nt = (ci.natoms + TILE - 1) / TILE;
+    c->ntile.push_back(nt);
+    ntiles += nt;
+    N += ci.natoms;
+    need_bins[k] = bins_for(H, rcs);
+    dens = std::max(dens, ci.natoms / (H[0] * H[4] * H[8]));
+  }
+  if (N > (1ll << 31) - 1) return bail(fail(c, RCELL_ERR_ARG, "too many atoms"));
+  c->N = N;
+  c->npad = (N + 63) / 64 * 64;
+  c->ntiles = ntiles;
+
+  // ---- stream and memory
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(c, RCELL_ERR_DEVICE, "hipStreamCreate failed"));
+    c->own_stream = true;
+  }
+  const size_t fsz = sizeof(double);
+  const size_t ssz = c->fp64 ? sizeof(S64) : sizeof(int4);
+  int e;
+  char *f0, *s0, *s1, *sbp;
+  if ((e = dalloc(c, &c->x, N)) || (e = dalloc(c, &c->y, N)) || (e = dalloc(c, &c->z, N)) ||
+      (e = dalloc(c, &c->vx, N)) || (e = dalloc(c, &c->vy, N)) || (e = dalloc(c, &c->vz, N)) ||
+      (e = dalloc(c, &f0, 3 * fsz * N)) || (e = dalloc(c, &s0, ssz * N)) || (e = dalloc(c, &s1, ssz * N)) ||
+      (e = dalloc(c, &sbp, ssz * N)) || (e = dalloc(c, &c->bond, N)) || (e = dalloc(c, &c->nn, N)) ||
+      (e = dalloc(c, &c->abin, N)) || (e = dalloc(c, &c->binned, N)) ||
+      (e = dalloc(c, &c->cells, ncells)) || (e = dalloc(c, &c->tiles, ntiles)) || (e = dalloc(c, &c->parts, ntiles)) ||
+      (e = dalloc(c, &c->stage, ncells)) || (e = dalloc(c, &c->dscratch, (size_t)17 * ncells)) ||
+      (e = dalloc(c, &c->iscratch, (size_t)2 * ncells)) || (e = dalloc(c, &c->lscratch, (size_t)2 * ncells)))
+    return bail(e);
+  c->fx = f0; c->fy = f0 + fsz * N; c->fz = f0 + 2 * fsz * N;
+  c->s[0] = s0; c->s[1] = s1; c->sb = sbp;
+  if ((e = ensure_list_capacity(c, list_capacity(dens, rcs)))) return bail(e);
+
+  // ---- marshal the initial state (AoS -> SoA), bonds -> per-atom partner slots
+  std::vector<double> hx(N), hy(N), hz(N), hvx(N, 0.0), hvy(N, 0.0), hvz(N, 0.0);
+  std::vector<int4> hb(N, make_int4(-1, -1, -1, -1));
+  std::vector<Tile> tl;
+  tl.reserve(ntiles);
+  for (int k = 0; k < ncells; ++k) {
+    const rcell_cell_init& ci = cells[k];
+    const long long o = c->off[k];
+    for (int i = 0; i < ci.natoms; ++i) {
+      hx[o + i] = ci.x[3 * i]; hy[o + i] = ci.x[3 * i + 1]; hz[o + i] = ci.x[3 * i + 2];
+      if (!std::isfinite(hx[o + i]) || !std::isfinite(hy[o + i]) || !std::isfinite(hz[o + i]))
+        return bail(fail(c, RCELL_ERR_ARG, "non-finite position in cell " + std::to_string(k)));
+      if (ci.v) { hvx[o + i] = ci.v[3 * i]; hvy[o + i] = ci.v[3 * i + 1]; hvz[o + i] = ci.v[3 * i + 2]; }
+    }
+    for (int b = 0; b < ci.nbonds; ++b) {
+      const int i = ci.bonds[2 * b], j = ci.bonds[2 * b + 1];
+      if (i < 0 || j < 0 || i >= ci.natoms || j >= ci.natoms || i == j)
+        return bail(fail(c, RCELL_ERR_ARG, "bad bond index in cell " + std::to_string(k)));
+      for (int side = 0; side < 2; ++side) {
+        const int a = side ? j : i, partner = side ? i : j;
+        int* slot = &hb[o + a].x;
+        int q = 0;
+        while (q < 4 && slot[q] >= 0) ++q;
+        if (q == 4) return bail(fail(c, RCELL_ERR_ARG, "more than 4 bonds on one atom in cell " + std::to_string(k)));
+        slot[q] = partner;
+      }
+    }
+    for (int t = 0; t < c->ntile[k]; ++t)
+      tl.push_back(Tile{k, (int)(o + t * TILE), std::min(TILE, ci.natoms - t * TILE), 0});
+  }
+  std::vector<CellDev> hc(ncells);
+  for (int k = 0; k < ncells; ++k) {
+    CellDev& C = hc[k];
+    std::memset(&C, 0, sizeof(C));
+    std::memcpy(C.H, cells[k].H0, sizeof(C.H));
+    for (int q = 0; q < 9; ++q) C.Rprev[q] = C.Q[q] = C.R[q] = C.F[q] = (q % 4 == 0) ? 1.0 : 0.0;
+    C.J = 1.0;
+    C.off = c->off[k]; C.n = c->n[k]; C.tile_off = c->tile_off[k]; C.ntile = c->ntile[k];
+  }
+  const size_t nb = sizeof(double) * N;
+  if (hipMemcpyAsync(c->x, hx.data(), nb, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->y, hy.data(), nb, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->z, hz.data(), nb, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->vx, hvx.data(), nb, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->vy, hvy.data(), nb, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->vz, hvz.data(), nb, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->bond, hb.data(), sizeof(int4) * N, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->tiles, tl.data(), sizeof(Tile) * ntiles, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->cells, hc.data(), sizeof(CellDev) * ncells, hipMemcpyHostToDevice, c->stream) ||
+      hipMemsetAsync(f0, 0, 3 * fsz * N, c->stream) || hipMemsetAsync(s0, 0, ssz * N, c->stream) ||
+      hipMemsetAsync(s1, 0, ssz * N, c->stream) || hipStreamSynchronize(c->stream))
+    return bail(fail(c, RCELL_ERR_DEVICE, "initial upload failed"));
+  if ((e = layout_bins(c, need_bins))) return bail(e);
+  hipLaunchKernelGGL(k_set_box, dim3((ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, ncells, rcs);
+  if ((e = prime(c))) return bail(e);
+  Gathered g;
+  if ((e = gather(c, g))) return bail(e);
+  if ((e = first_error(c, g.status))) return bail(e);
+  *out = c;
+  return RCELL_OK;
+}
+
+int rcell_set_deformation(rcell_ctx* c, const double* F) {
+  if (!c || !F) return c ? fail(c, RCELL_ERR_ARG, "F is NULL") : RCELL_ERR_ARG;
+  for (int k = 0; k < 9 * c->ncells; ++k)
+    if (!std::isfinite(F[k])) return fail(c, RCELL_ERR_BAD_F, "non-finite F in cell " + std::to_string(k / 9));
+  double* Fd = c->dscratch;
+  HIPCHK(c, hipMemcpyAsync(Fd, F, sizeof(double) * 9 * c->ncells, hipMemcpyHostToDevice, c->stream));
+  return deformation_common(c, Fd);
+}
+
+int rcell_set_deformation_dev(rcell_ctx* c, const void* F_dev) {
+  if (!c || !F_dev) return c ? fail(c, RCELL_ERR_ARG, "F_dev is NULL") : RCELL_ERR_ARG;
+  return deformation_common(c, (const double*)F_dev);
+}
+
+int rcell_run(rcell_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return c ? fail(c, RCELL_ERR_ARG, "nsteps < 0") : RCELL_ERR_ARG;
+  if (nsteps == 0) return RCELL_OK;
+  launch_start(c);
+  launch_reduce(c, RED_START);
+  launch_build(c);
+  for (int k = 1; k <= nsteps; ++k) {
+    const bool last = k == nsteps;
+    launch_force(c, last ? MODE_LAST : MODE_STEP);
+    launch_reduce(c, last ? RED_LAST : RED_STEP);
+    if (!last) {
+      c->cur = 1 - c->cur;
+      launch_build(c);
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  return RCELL_OK;
+}
+
+int rcell_get_stress_dev(rcell_ctx* c, void* sigma_dev, void* P_dev) {
+  if (!c || !sigma_dev) return c ? fail(c, RCELL_ERR_ARG, "sigma_dev is NULL") : RCELL_ERR_ARG;
+  hipLaunchKernelGGL(k_stress_out, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, c->ncells,
+                     (double*)sigma_dev, (double*)P_dev);
+  HIPCHK(c, hipGetLastError());
+  return RCELL_OK;
+}
+
+int rcell_get_stress(rcell_ctx* c, double* sigma, double* P) {
+  if (!c || !sigma) return c ? fail(c, RCELL_ERR_ARG, "sigma is NULL") : RCELL_ERR_ARG;
+  const int nc = c->ncells;
+  double* sd = c->dscratch;
+  double* pd = c->dscratch + 6 * nc;
+  int e = rcell_get_stress_dev(c, sd, P ? pd : nullptr);
+  if (e) return e;
+  HIPCHK(c, hipMemcpyAsync(sigma, sd, sizeof(double) * 6 * nc, hipMemcpyDeviceToHost, c->stream));
+  if (P) HIPCHK(c, hipMemcpyAsync(P, pd, sizeof(double) * 9 * nc, hipMemcpyDeviceToHost, c->stream));
+  Gathered g;
+  if ((e = gather(c, g))) return e;
+  return first_error(c, g.status);
+}
+
+int rcell_destroy(rcell_ctx* c) {
+  if (!c) return RCELL_OK;
+  destroy_all(c);
+  delete c;
+  return RCELL_OK;
+}
+
+const char* rcell_last_error(const rcell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int rcell_get_status(rcell_ctx* c, int32_t* status) {
+  if (!c || !status) return c ? fail(c, RCELL_ERR_ARG, "status is NULL") : RCELL_ERR_ARG;
+  Gathered g;
+  int e = gather(c, g);
+  if (e) return e;
+  std::copy(g.status.begin(), g.status.end(), status);
+  return RCELL_OK;
+}
+
+int rcell_get_forces(rcell_ctx* c, int32_t cell, double* f) {
+  if (!c || !f || cell < 0 || cell >= c->ncells) return c ? fail(c, RCELL_ERR_ARG, "bad cell or f") : RCELL_ERR_ARG;
+  const long long o = c->off[cell], n = c->n[cell];
+  const size_t fsz = sizeof(double);
+  std::vector<char> buf(3 * fsz * n);
+  void* src[3] = {c->fx, c->fy, c->fz};
+  for (int q = 0; q < 3; ++q)
+    HIPCHK(c, hipMemcpyAsync(buf.data() + q * fsz * n, (char*)src[q] + fsz * o, fsz * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int q = 0; q < 3; ++q)
+    for (long long i = 0; i < n; ++i)
+      f[3 * i + q] = ((const double*)buf.data())[q * n + i];
+  return RCELL_OK;
+}
+
+int rcell_get_state(rcell_ctx* c, int32_t cell, double* x, double* v, double* H, double* Rprev, int64_t* step) {
+  if (!c || cell < 0 || cell >= c->ncells) return c ? fail(c, RCELL_ERR_ARG, "bad cell") : RCELL_ERR_ARG;
+  const long long o = c->off[cell], n = c->n[cell];
+  std::vector<double> buf(6 * n);
+  double* src[6] = {c->x, c->y, c->z, c->vx, c->vy, c->vz};
+  for (int q = 0; q < 6; ++q)
+    HIPCHK(c, hipMemcpyAsync(buf.data() + q * n, src[q] + o, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  CellDev C;
+  HIPCHK(c, hipMemcpyAsync(&C, c->cells + cell, sizeof(CellDev), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (long long i = 0; i < n; ++i)
+    for (int q = 0; q < 3; ++q) {
+      if (x) x[3 * i + q] = buf[q * n + i];
+      if (v) v[3 * i + q] = buf[(3 + q) * n + i];
+    }
+  if (H) std::memcpy(H, C.H, sizeof(C.H));
+  if (Rprev) std::memcpy(Rprev, C.Rprev, sizeof(C.Rprev));
+  if (step) *step = C.step;
+  return RCELL_OK;
+}
+
+int rcell_set_state(rcell_ctx* c, int32_t cell, const double* x, const double* v, const double* H,
+                    const double* Rprev, int64_t step) {
+  if (!c || cell < 0 || cell >= c->ncells || !x || !v || !H || !Rprev)
+    return c ? fail(c, RCELL_ERR_ARG, "bad cell or NULL argument") : RCELL_ERR_ARG;
+  if (!(H[0] > 0 && H[4] > 0 && H[8] > 0) || H[3] != 0 || H[6] != 0 || H[7] != 0)
+    return fail(c, RCELL_ERR_STATE, "H must be upper triangular with positive diagonal");
+  const double rcs = c->p.rc + c->p.skin;
+  if (0.5 * width_min(H) < rcs) return fail(c, RCELL_ERR_BOX, "box too small for rc + skin");
+  const long long o = c->off[cell], n = c->n[cell];
+  std::vector<int> need(c->bin_cap);
+  need[cell] = std::max(need[cell], bins_for(H, rcs));
+  int e;
+  if (need[cell] > c->bin_cap[cell] && (e = layout_bins(c, need))) return e;
+  if ((e = ensure_list_capacity(c, list_capacity(n / (H[0] * H[4] * H[8]), rcs)))) return e;
+  std::vector<double> buf(6 * n);
+  for (long long i = 0; i < n; ++i)
+    for (int q = 0; q < 3; ++q) { buf[q * n + i] = x[3 * i + q]; buf[(3 + q) * n + i] = v[3 * i + q]; }
+  double* dst[6] = {c->x, c->y, c->z, c->vx, c->vy, c->vz};
+  for (int q = 0; q < 6; ++q)
+    HIPCHK(c, hipMemcpyAsync(dst[q] + o, buf.data() + q * n, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  CellDev C;
+  HIPCHK(c, hipMemcpyAsync(&C, c->cells + cell, sizeof(CellDev), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::memcpy(C.H, H, sizeof(C.H));
+  std::memcpy(C.Rprev, Rprev, sizeof(C.Rprev));
+  C.step = step;
+  C.status = 0;
+  HIPCHK(c, hipMemcpyAsync(c->cells + cell, &C, sizeof(CellDev), hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_set_box, dim3(1), dim3(64), 0, c->stream, c->cells, cell, 1, rcs);
+  if ((e = prime(c))) return e;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RCELL_OK;
+}
+
+int rcell_get_energy(rcell_ctx* c, double* pe, double* ke) {
+  if (!c) return RCELL_ERR_ARG;
+  Gathered g;
+  int e = gather(c, g);
+  if (e) return e;
+  if (pe) std::copy(g.pe.begin(), g.pe.end(), pe);
+  if (ke) {
+    const MDArgs a = make_args(c);
+    double* kd = c->dscratch;
+    hipLaunchKernelGGL(k_kinetic, dim3(c->ncells), dim3(RED_NT), 0, c->stream, a, kd);
+    HIPCHK(c, hipMemcpyAsync(ke, kd, sizeof(double) * c->ncells, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return RCELL_OK;
+}
+
+int rcell_get_box(rcell_ctx* c, int32_t cell, double* H, double* Q, double* R, double* J) {
+  if (!c || cell < 0 || cell >= c->ncells) return c ? fail(c, RCELL_ERR_ARG, "bad cell") : RCELL_ERR_ARG;
+  CellDev C;
+  HIPCHK(c, hipMemcpyAsync(&C, c->cells + cell, sizeof(CellDev), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (H) std::memcpy(H, C.H, sizeof(C.H));
+  if (Q) std::memcpy(Q, C.Q, sizeof(C.Q));
+  if (R) std::memcpy(R, C.R, sizeof(C.R));
+  if (J) *J = C.J;
+  return RCELL_OK;
+}
+
+int rcell_get_rebuilds(rcell_ctx* c, int64_t* count) {
+  if (!c || !count) return RCELL_ERR_ARG;
+  Gathered g;
+  int e = gather(c, g);
+  if (e) return e;
+  long long s = 0;
+  for (long long v : g.nreb) s += v;
+  *count = s;
+  return RCELL_OK;
+}
+
+int rcell_set_lanes(rcell_ctx* c, int32_t lanes) {
+  if (!c) return RCELL_ERR_ARG;
+  if (lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16) {
+    c->lanes = lanes;
+    return RCELL_OK;
+  }
+  if (lanes != 0) return fail(c, RCELL_ERR_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
+  // autotune: time the force pass (no state written) for each variant, keep the fastest
+  hipEvent_t t0, t1;
+  HIPCHK(c, hipEventCreate(&t0));
+  HIPCHK(c, hipEventCreate(&t1));
+  float best = 1e30f;
+  int best_l = c->lanes;
+  for (int l : {1, 2, 4, 8, 16}) {
+    launch_force(c, MODE_DRY, l);
+    HIPCHK(c, hipEventRecord(t0, c->stream));
+    for (int r = 0; r < 5; ++r) launch_force(c, MODE_DRY, l);
+    HIPCHK(c, hipEventRecord(t1, c->stream));
+    HIPCHK(c, hipEventSynchronize(t1));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, t0, t1));
+    if (ms < best) { best = ms; best_l = l; }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  c->lanes = best_l;
+  return RCELL_OK;
+}
+
+int rcell_get_lanes(rcell_ctx* c, int32_t* lanes) {
+  if (!c || !lanes) return RCELL_ERR_ARG;
+  *lanes = c->lanes;
+  return RCELL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,212 @@
+"""Python binding of the librcell C ABI (include/rcell.h): argument marshalling only.
+
+Every computation happens in the HIP library.  There is no fallback: if librcell.so has not
+been built (``python -m paper_1902_09171_amd.build``) or cannot be loaded, importing the binding
+raises.  Device memory and streams may come from PyTorch; the library itself only sees raw
+pointers.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librcell.so")
+
+OK, ERR_ARG, ERR_BAD_F, ERR_BOX, ERR_BOND, ERR_NONFINITE, ERR_OOM, ERR_DEVICE, ERR_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+POTENTIALS = {"kg": 1, "sc_eam": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+# every entry point that include/rcell.h declares
+EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev", "rcell_run",
+           "rcell_get_stress", "rcell_get_stress_dev", "rcell_destroy", "rcell_last_error",
+           "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
+           "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
+           "rcell_get_lanes"]
+
+
+class RCellError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"rcell error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("potential", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("temperature", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("mass", ctypes.c_double), ("kB", ctypes.c_double), ("mvv2e", ctypes.c_double),
+                ("rc", ctypes.c_double), ("skin", ctypes.c_double),
+                ("lj_eps", ctypes.c_double), ("lj_sigma", ctypes.c_double),
+                ("fene_K", ctypes.c_double), ("fene_R0", ctypes.c_double),
+                ("sc_eps", ctypes.c_double), ("sc_a", ctypes.c_double), ("sc_c", ctypes.c_double),
+                ("sc_n", ctypes.c_int32), ("sc_m", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("include_kinetic", ctypes.c_int32)]
+
+
+class CellInit(ctypes.Structure):
+    _fields_ = [("natoms", ctypes.c_int32), ("nbonds", ctypes.c_int32),
+                ("H0", ctypes.c_void_p), ("x", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("bonds", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1902_09171_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "rcell_create": [vp, vp, i32, vp, vp], "rcell_set_deformation": [vp, vp],
+            "rcell_set_deformation_dev": [vp, vp], "rcell_run": [vp, i32],
+            "rcell_get_stress": [vp, vp, vp], "rcell_get_stress_dev": [vp, vp, vp],
+            "rcell_destroy": [vp], "rcell_last_error": [vp], "rcell_get_status": [vp, vp],
+            "rcell_get_forces": [vp, i32, vp], "rcell_get_state": [vp, i32, vp, vp, vp, vp, vp],
+            "rcell_set_state": [vp, i32, vp, vp, vp, vp, i64], "rcell_get_energy": [vp, vp, vp],
+            "rcell_get_box": [vp, i32, vp, vp, vp, vp], "rcell_get_rebuilds": [vp, vp],
+            "rcell_set_lanes": [vp, i32], "rcell_get_lanes": [vp, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.rcell_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def params_struct(p: dict) -> Params:
+    s = Params()
+    for name, _ in Params._fields_:
+        val = p[name]
+        if name == "potential" and isinstance(val, str):
+            val = POTENTIALS[val]
+        if name == "precision" and isinstance(val, str):
+            val = PRECISIONS[val]
+        setattr(s, name, val)
+    return s
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a.reshape(shape) if shape is not None else a
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+class RCellBatch:
+    """A batch of r-cells on the current GPU (one rcell_ctx).
+
+    params: dict with the rcell_params fields; cells: list of {"x", "v", "bonds", "H0"}.
+    stream: optional hipStream_t handle (int), e.g. torch.cuda.current_stream().cuda_stream.
+    """
+
+    def __init__(self, params, cells, stream=None):
+        L = load()
+        self.params = dict(params)
+        self.ncells = len(cells)
+        self.natoms = [len(c["x"]) for c in cells]
+        self._keep = []
+        inits = (CellInit * self.ncells)()
+        for k, c in enumerate(cells):
+            H0 = _f64(c["H0"], (3, 3))
+            x = _f64(c["x"], (-1, 3))
+            v = None if c.get("v") is None else _f64(c["v"], (-1, 3))
+            b = np.ascontiguousarray(np.asarray(c.get("bonds", np.zeros((0, 2))), np.int32).reshape(-1, 2))
+            self._keep += [H0, x, v, b]
+            inits[k].natoms = len(x)
+            inits[k].nbonds = len(b)
+            inits[k].H0 = _p(H0)
+            inits[k].x = _p(x)
+            inits[k].v = _p(v)
+            inits[k].bonds = _p(b) if len(b) else None
+        ps = params_struct(params)
+        h = ctypes.c_void_p()
+        st = L.rcell_create(ctypes.byref(ps), inits, self.ncells, stream, ctypes.byref(h))
+        self._keep = []
+        if st != OK:
+            raise RCellError(st, (L.rcell_last_error(None) or b"").decode())
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rcell_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise RCellError(st, (load().rcell_last_error(self._h) or b"").decode())
+
+    def set_deformation(self, F):
+        F = _f64(F, (self.ncells, 3, 3))
+        self._check(load().rcell_set_deformation(self._h, _p(F)))
+
+    def set_deformation_dev(self, F_dev_ptr):
+        self._check(load().rcell_set_deformation_dev(self._h, F_dev_ptr))
+
+    def run(self, nsteps):
+        self._check(load().rcell_run(self._h, int(nsteps)))
+
+    def get_stress(self, with_P=False):
+        s = np.zeros((self.ncells, 6))
+        P = np.zeros((self.ncells, 3, 3)) if with_P else None
+        self._check(load().rcell_get_stress(self._h, _p(s), _p(P)))
+        return (s, P) if with_P else s
+
+    def get_stress_dev(self, sigma_dev_ptr, P_dev_ptr=None):
+        self._check(load().rcell_get_stress_dev(self._h, sigma_dev_ptr, P_dev_ptr))
+
+    def status(self):
+        s = np.zeros(self.ncells, np.int32)
+        self._check(load().rcell_get_status(self._h, _p(s)))
+        return s
+
+    def get_forces(self, cell):
+        f = np.zeros((self.natoms[cell], 3))
+        self._check(load().rcell_get_forces(self._h, cell, _p(f)))
+        return f
+
+    def get_state(self, cell):
+        n = self.natoms[cell]
+        x, v, H, Rp = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((3, 3)), np.zeros((3, 3))
+        step = ctypes.c_int64(0)
+        self._check(load().rcell_get_state(self._h, cell, _p(x), _p(v), _p(H), _p(Rp), ctypes.byref(step)))
+        return dict(x=x, v=v, H=H, Rprev=Rp, step=step.value)
+
+    def set_state(self, cell, x, v, H, Rprev, step):
+        x, v, H, Rp = _f64(x, (-1, 3)), _f64(v, (-1, 3)), _f64(H, (3, 3)), _f64(Rprev, (3, 3))
+        self._check(load().rcell_set_state(self._h, cell, _p(x), _p(v), _p(H), _p(Rp), int(step)))
+
+    def get_energy(self):
+        pe, ke = np.zeros(self.ncells), np.zeros(self.ncells)
+        self._check(load().rcell_get_energy(self._h, _p(pe), _p(ke)))
+        return pe, ke
+
+    def get_box(self, cell):
+        H, Q, R = np.zeros((3, 3)), np.zeros((3, 3)), np.zeros((3, 3))
+        J = ctypes.c_double(0)
+        self._check(load().rcell_get_box(self._h, cell, _p(H), _p(Q), _p(R), ctypes.byref(J)))
+        return H, Q, R, J.value
+
+    def rebuilds(self):
+        c = ctypes.c_int64(0)
+        self._check(load().rcell_get_rebuilds(self._h, ctypes.byref(c)))
+        return c.value
+
+    def set_lanes(self, lanes):
+        self._check(load().rcell_set_lanes(self._h, int(lanes)))
+        return self.lanes()
+
+    def lanes(self):
+        l = ctypes.c_int32(0)
+        self._check(load().rcell_get_lanes(self._h, ctypes.byref(l)))
+        return l.value

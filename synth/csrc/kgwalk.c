@@ -107,3 +107,74 @@ int kg_random_walk(double L, int32_t nchains, const int32_t* lens, double bond, 
   head_ = next_ = NULL;
   return 0;
 }
+
+/* Geometric overlap relaxation (no potential, no forces): repeated Jacobi sweeps that move every
+ * non-bonded pair closer than dpush apart by a fraction of the deficit, then pull every bond back
+ * towards bond_len.  Stops after `iters` sweeps or when no pair is closer than dpush.
+ * x: n*3 positions in [0,L)^3 (updated, rewrapped); bonds: nbonds*2 indices.
+ * Returns the smallest non-bonded distance found in the last sweep, or -1 on bad input. */
+double kg_relax(double L, int32_t n, double* x, int32_t nbonds, const int32_t* bonds, double dpush,
+                double bond_len, int32_t iters) {
+  if (L <= 0 || n < 0 || dpush <= 0 || iters < 0) return -1.0;
+  int32_t* part = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * 4 * sizeof(int32_t));
+  double* dx = (double*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+  if (!part || !dx) { free(part); free(dx); return -1.0; }
+  for (int64_t k = 0; k < 4 * (int64_t)n; ++k) part[k] = -1;
+  for (int32_t b = 0; b < nbonds; ++b)
+    for (int s = 0; s < 2; ++s) {
+      int32_t a = bonds[2 * b + s], o = bonds[2 * b + 1 - s];
+      for (int q = 0; q < 4; ++q) if (part[4 * a + q] < 0) { part[4 * a + q] = o; break; }
+    }
+  L_ = L; g_ = (int)floor(L / dpush); if (g_ < 1) g_ = 1; if (g_ > 1024) g_ = 1024;
+  size_t ncell = (size_t)g_ * g_ * g_;
+  head_ = (int*)malloc(ncell * sizeof(int));
+  next_ = (int*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+  double dmin_seen = 1e300;
+  for (int it = 0; it < iters; ++it) {
+    for (size_t c = 0; c < ncell; ++c) head_[c] = -1;
+    for (int32_t i = n - 1; i >= 0; --i) {
+      int cell = (gidx(x[3 * i]) * g_ + gidx(x[3 * i + 1])) * g_ + gidx(x[3 * i + 2]);
+      next_[i] = head_[cell]; head_[cell] = i;
+    }
+    for (int64_t k = 0; k < 3 * (int64_t)n; ++k) dx[k] = 0.0;
+    dmin_seen = 1e300;
+#pragma omp parallel for schedule(static) reduction(min : dmin_seen)
+    for (int32_t i = 0; i < n; ++i) {
+      int c0 = gidx(x[3 * i]), c1 = gidx(x[3 * i + 1]), c2 = gidx(x[3 * i + 2]);
+      int span = g_ < 3 ? 0 : 1;
+      for (int a = -span; a <= span; ++a)
+        for (int b = -span; b <= span; ++b)
+          for (int c = -span; c <= span; ++c) {
+            int cell = g_ < 3 ? -1 : (((c0 + a + g_) % g_) * g_ + (c1 + b + g_) % g_) * g_ + (c2 + c + g_) % g_;
+            int j = g_ < 3 ? 0 : head_[cell];
+            for (; g_ < 3 ? j < n : j >= 0; j = g_ < 3 ? j + 1 : next_[j]) {
+              if (j == i) continue;
+              int bonded = 0;
+              for (int q = 0; q < 4; ++q) bonded |= part[4 * i + q] == j;
+              if (bonded) continue;
+              double d[3], r2 = 0;
+              for (int k = 0; k < 3; ++k) { d[k] = x[3 * j + k] - x[3 * i + k]; d[k] -= L * nearbyint(d[k] / L); r2 += d[k] * d[k]; }
+              double r = sqrt(r2);
+              if (r < dmin_seen) dmin_seen = r;
+              if (r < dpush && r > 1e-12)
+                for (int k = 0; k < 3; ++k) dx[3 * i + k] -= 0.25 * (dpush - r) * d[k] / r;
+            }
+          }
+      for (int q = 0; q < 4; ++q) {
+        int32_t j = part[4 * i + q];
+        if (j < 0) continue;
+        double d[3], r2 = 0;
+        for (int k = 0; k < 3; ++k) { d[k] = x[3 * j + k] - x[3 * i + k]; d[k] -= L * nearbyint(d[k] / L); r2 += d[k] * d[k]; }
+        double r = sqrt(r2);
+        if (r > 1e-12)
+          for (int k = 0; k < 3; ++k) dx[3 * i + k] += 0.5 * (r - bond_len) * d[k] / r;
+      }
+    }
+    for (int32_t i = 0; i < n; ++i)
+      for (int k = 0; k < 3; ++k) x[3 * i + k] = wrap1(x[3 * i + k] + dx[3 * i + k]);
+    if (dmin_seen >= dpush) break;
+  }
+  free(head_); free(next_); free(part); free(dx);
+  head_ = next_ = NULL;
+  return dmin_seen;
+}
