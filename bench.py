@@ -1,0 +1,170 @@
+"""Throughput of batched r-cell MD on one MI355X.
+
+A step is one finite-element load step of the copper-element workload: for all 8 r-cells
+(4000-atom FCC copper, Sutton-Chen EAM, 300 K Langevin, dt = 1 fs, mixed precision) the device
+resident deformation gradient is QR-decomposed and the boxes remapped, 100 MD steps run
+(neighbour builds, two-pass EAM forces fused with the Langevin velocity-Verlet update, per-cell
+stress reduction), and the window-averaged stress is rotated to the FE frame into device memory.
+Inputs are resident in HBM before the timed region.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MD_PER_LOAD = 100
+PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s
+# algorithmic FLOPs per unique pair inside the cutoff (FMA = 2, other ops 1): Sutton-Chen force
+# pass (separation 3, r^2 5, 1/r 2, a/r 1, t^6 3, t^9 2, pair scalar 7, forces on both atoms 12,
+# virial 15, pair energy 3) and density pass (separation 3, r^2 5, 1/r 2, a/r 1, t^6 3, shift 1,
+# both densities 2)
+FLOP_FORCE_PER_PAIR = 53
+FLOP_DENSITY_PER_PAIR = 17
+PAIRS_PER_ATOM = 67           # unique neighbours within 1.95 a in FCC copper
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("md_device.h", "rcell_md.hip"):
+        with open(os.path.join(ROOT, "paper_1902_09171_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it matches the source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cu_element.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, sample_steps):
+    """The FP64 oracle on the host cores, on the first load step of the same workload."""
+    from oracle import core
+    ncells = len(cfg["cells"])
+    threads = core.threads(min(ncells, os.cpu_count() or 1))
+    ob = core.OracleBatch(cfg["params"], cfg["cells"])
+    ob.set_deformation(cfg["F_path"][0])
+    ob.get_stress()
+    t0 = time.perf_counter()
+    ob.run(sample_steps)
+    dt = time.perf_counter() - t0
+    natoms = sum(len(c["x"]) for c in cfg["cells"])
+    return dict(value=natoms * sample_steps / dt, unit="atom-steps/s", cores=threads, kind="oracle",
+                sample=f"{ncells} cells x {natoms // ncells} atoms x {sample_steps} MD steps of the first load step"), ob.get_stress()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=25)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0 = autotune)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described "
+                                   "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1902_09171_amd import rcell
+    from synth import configs
+
+    cfg = configs.cu_element()
+    ncells = len(cfg["cells"])
+    natoms = sum(len(c["x"]) for c in cfg["cells"])
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    g = rcell.RCellBatch(cfg["params"], cfg["cells"], stream=stream.cuda_stream)
+    nload = len(cfg["F_path"])
+    F_dev = torch.tensor(np.ascontiguousarray(cfg["F_path"]), dtype=torch.float64, device=dev)
+    sig_dev = torch.zeros((ncells, 6), dtype=torch.float64, device=dev)
+    P_dev = torch.zeros((ncells, 9), dtype=torch.float64, device=dev)
+
+    g.set_deformation_dev(F_dev[0].data_ptr())
+    lanes = g.set_lanes(args.lanes)
+
+    def load_step(k):
+        g.set_deformation_dev(F_dev[k % nload].data_ptr())
+        g.run(MD_PER_LOAD)
+        g.get_stress_dev(sig_dev.data_ptr(), P_dev.data_ptr())
+
+    for k in range(args.warmup):
+        load_step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        load_step(args.warmup + k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # kernel durations: the same load steps again, each force-pass launch bracketed by HIP events
+    # on the library's stream (a separate pass, so the events do not perturb the throughput)
+    nprof = min(args.steps, 10)
+    g.prof_enable(True)
+    g.prof_read(0); g.prof_read(1)
+    for k in range(nprof):
+        load_step(args.warmup + args.steps + k)
+    force_ms, force_n = g.prof_read(0)
+    rho_ms, rho_n = g.prof_read(1)
+    g.prof_enable(False)
+    st = g.status()
+    if np.any(st != 0):
+        raise SystemExit(f"cell status errors during the bench: {st.tolist()}")
+    elapsed = t1 - t0
+    atom_steps = natoms * MD_PER_LOAD * args.steps
+    value = atom_steps / elapsed
+
+    # roofline of the dominant kernel (the EAM force pass with the fused integrator)
+    avg_s = force_ms / 1e3 / max(force_n, 1)
+    flop_launch = FLOP_FORCE_PER_PAIR * PAIRS_PER_ATOM * natoms
+    achieved = flop_launch / avg_s
+    traffic = traffic_from_profiles("k_force_eam")
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": "k_force_eam",
+                "avg_us": avg_s * 1e6, "launches": force_n,
+                "density_pass_avg_us": rho_ms / 1e3 / max(rho_n, 1) * 1e6,
+                "flop_per_launch": flop_launch}
+
+    out = {"metric": "atom-steps/s batched r-cell MD", "value": value, "unit": "atom-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 pair forces, f64 positions/integration/stress",
+           "data": "synthetic",
+           "config": {"workload": "cu_element: 8 FCC copper r-cells x 4000 atoms (one hex8 element, "
+                                  "2x2x2 Gauss points), Sutton-Chen EAM, 300 K, dt 1 fs, rotated "
+                                  "uniaxial F ramp to 5 %, 100 MD steps per load step",
+                      "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
+                      "lanes_per_atom": lanes},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        cb, s_ora = cpu_baseline(cfg, args.cpu_sample_steps)
+        # the same sample on the GPU from the same initial state: stress error of this run
+        g2 = rcell.RCellBatch(cfg["params"], cfg["cells"], stream=stream.cuda_stream)
+        g2.set_lanes(lanes)
+        g2.set_deformation(cfg["F_path"][0])
+        g2.get_stress()
+        g2.run(args.cpu_sample_steps)
+        s_gpu = g2.get_stress()
+        fro = np.sqrt((s_ora[:, :3] ** 2).sum(1) + 2 * (s_ora[:, 3:] ** 2).sum(1))
+        out["cpu_baseline"] = cb
+        out["stress_rel_err_vs_oracle"] = float((np.abs(s_gpu - s_ora).max(1) / fro).max())
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

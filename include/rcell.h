@@ -142,6 +142,15 @@ int rcell_get_rebuilds(rcell_ctx* ctx, int64_t* count);
  * current state (advances no state), or 1, 2, 4, 8, 16 */
 int rcell_set_lanes(rcell_ctx* ctx, int32_t lanes);
 int rcell_get_lanes(rcell_ctx* ctx, int32_t* lanes);
+/* MD steps inside a run are replayed from captured HIP graphs of `steps` steps (even; default
+ * 10); 0 launches every kernel individually.  Results are identical either way. */
+int rcell_set_graph_steps(rcell_ctx* ctx, int32_t steps);
+/* kernel timing: while enabled, each launch of the pair-force pass (which = 0: the force kernel
+ * with the fused Langevin/Verlet update; which = 1: the EAM density pass) is bracketed by HIP
+ * events on the context's stream (8192 events are created when enabling; graphs are not used).  rcell_prof_read synchronises, returns the summed duration in
+ * milliseconds and the number of launches since the last read, and resets both. */
+int rcell_prof_enable(rcell_ctx* ctx, int32_t on);
+int rcell_prof_read(rcell_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -74,6 +74,7 @@ struct MDArgs {
   Part* parts;
   int ntiles, ncells;
   int* abin; int* bcount; int* bstart; int* bnum; int* bfill; int* binned;
+  long long bins_total;
   // integrator constants (computed once on the host, documented expressions)
   double dt, h, drag, c24, mmv, half_skin2, rcs2;
   uint32_t key0, key1;
@@ -608,13 +609,10 @@ __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
   write_part<TILE>(a.parts, Z, Z, 0.0, xi, maxd2, 0, psh);
 }
 
-// Per-cell reduction of the tile partials (one 256-thread block per cell, fixed order).
-constexpr int RED_NT = 256;
+// Per-cell reduction of the tile partials: one wave per cell, each lane sums every 64th tile
+// in order, then a fixed xor-shuffle tree (deterministic for a given tile count).
+constexpr int RED_NT = 64;
 __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
-  __shared__ double shd[RED_NT];
-  __shared__ long long shl[RED_NT];
-  __shared__ float shf[RED_NT];
-  __shared__ int shi[RED_NT];
   CellDev& C = a.cells[blockIdx.x];
   if (mode == RED_PRIME && !C.pending) return;
   double W[6] = {0, 0, 0, 0, 0, 0}, K[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
@@ -632,14 +630,11 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   }
   double r[13];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) r[q] = block_sum<RED_NT>(W[q], shd);
-#pragma unroll
-  for (int q = 0; q < 6; ++q) r[6 + q] = block_sum<RED_NT>(K[q], shd);
-  r[12] = block_sum<RED_NT>(pe, shd);
-  const long long x0 = block_sum_ll<RED_NT>(xi[0], shl), x1 = block_sum_ll<RED_NT>(xi[1], shl),
-                  x2 = block_sum_ll<RED_NT>(xi[2], shl);
-  const float md = block_max<RED_NT>(m, shf);
-  st = block_min_i<RED_NT>(st, shi);
+  for (int q = 0; q < 6; ++q) { r[q] = wave_sum(W[q]); r[6 + q] = wave_sum(K[q]); }
+  r[12] = wave_sum(pe);
+  const long long x0 = wave_sum(xi[0]), x1 = wave_sum(xi[1]), x2 = wave_sum(xi[2]);
+  const float md = wave_max(m);
+  st = wave_min(st);
   if (threadIdx.x != 0) return;
   if (st != 0 && C.status == 0) C.status = st;
   if (C.rebuild) C.nrebuild += 1;
@@ -677,7 +672,14 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
 }
 
 // ------------------------------------------------------------------ neighbour build
-// 1: wrap positions into the box, fixed-point S, bin in scaled space, histogram per cell
+// Neighbour build of the cells flagged for a rebuild, in four phases (each kernel exits at
+// once for cells that are not flagged):
+//   k_bin        per atom: wrap into the box, fixed-point S and the build reference, bin index
+//                in scaled space, histogram (tiles)
+//   k_bin_scan   exclusive scan of the histogram (one block per cell)
+//   k_bin_fill   scatter of cell-local indices into their bins (tiles)
+//   k_bin_sort   order every bin by atom index (one thread per bin), so that the neighbour lists
+//                and the force sums built from them are deterministic
 template <class P>
 __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
   const Tile t = a.tiles[blockIdx.x];
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
   double x = a.x[i], y = a.y[i], z = a.z[i];
   const double s0 = C.Hi[0] * x + C.Hi[1] * y + C.Hi[2] * z, s1 = C.Hi[4] * y + C.Hi[5] * z, s2 = C.Hi[8] * z;
   const double k0 = floor(s0), k1 = floor(s1), k2 = floor(s2);
-  if (k0 != 0.0 || k1 != 0.0 || k2 != 0.0) {      // x -= H k (lattice vector), H upper triangular
+  if (k0 != 0.0 || k1 != 0.0 || k2 != 0.0) {       // x -= H k (a lattice vector), H upper triangular
     x -= C.H[0] * k0 + C.H[1] * k1 + C.H[2] * k2;
     y -= C.H[4] * k1 + C.H[5] * k2;
     z -= C.H[8] * k2;
@@ -695,9 +697,9 @@ __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
   }
   double f[3];
   scaled_frac(C, x, y, z, f);
-  typename P::S s = P::make(f[0], f[1], f[2]);
-  P::store_xyz(a.s_cur, i, s);
-  P::store_xyz(a.sb, i, s);
+  const typename P::S sv = P::make(f[0], f[1], f[2]);
+  P::store_xyz(a.s_cur, i, sv);
+  P::store_xyz(a.sb, i, sv);
   int b[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) b[q] = min((int)(f[q] * C.nb[q]), C.nb[q] - 1);
@@ -706,36 +708,37 @@ __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
   atomicAdd(&a.bcount[C.bin_off + bin], 1);
 }
 
-// 2: exclusive scan of the bin histogram (one block per cell)
-constexpr int SCAN_NT = 256;
+constexpr int SCAN_NT = 1024;
 __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
   __shared__ int sh[SCAN_NT];
   const CellDev& C = a.cells[blockIdx.x];
   if (!C.rebuild) return;
   const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
+  int* cnt = a.bcount + C.bin_off;
   const int per = (nbins + SCAN_NT - 1) / SCAN_NT;
   const int lo = min(nbins, (int)threadIdx.x * per), hi = min(nbins, lo + per);
-  int s = 0;
-  for (int b = lo; b < hi; ++b) s += a.bcount[C.bin_off + b];
-  sh[threadIdx.x] = s;
+  int acc = 0;
+  for (int b = lo; b < hi; ++b) acc += cnt[b];
+  sh[threadIdx.x] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int q = 0; q < SCAN_NT; ++q) { const int v = sh[q]; sh[q] = acc; acc += v; }
+  // Hillis-Steele inclusive scan of the chunk sums in shared memory
+  for (int o = 1; o < SCAN_NT; o <<= 1) {
+    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
   }
-  __syncthreads();
-  int acc = sh[threadIdx.x];
+  acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0;
   for (int b = lo; b < hi; ++b) {
-    const int c = a.bcount[C.bin_off + b];
+    const int c = cnt[b];
     a.bstart[C.bin_off + b] = acc;
     a.bnum[C.bin_off + b] = c;
-    a.bcount[C.bin_off + b] = 0;
     a.bfill[C.bin_off + b] = 0;
+    cnt[b] = 0;                                      // ready for the next build
     acc += c;
   }
 }
 
-// 3: scatter cell-local atom indices into their bins
 __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   const Tile t = a.tiles[blockIdx.x];
   const CellDev& C = a.cells[t.cell];
@@ -746,20 +749,21 @@ __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
 
-// 4: order each bin by atom index, so that neighbour lists (and force sums) are deterministic
-__global__ __launch_bounds__(SCAN_NT) void k_bin_sort(MDArgs a) {
-  const CellDev& C = a.cells[blockIdx.x];
-  if (!C.rebuild) return;
-  const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
-  for (int b = threadIdx.x; b < nbins; b += SCAN_NT) {
-    int* p = a.binned + C.off + a.bstart[C.bin_off + b];
-    const int n = a.bnum[C.bin_off + b];
-    for (int u = 1; u < n; ++u) {
-      const int v = p[u];
-      int q = u - 1;
-      while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
-      p[q + 1] = v;
-    }
+// one thread per bin slot of every cell (grid over the bin capacity): insertion sort in place
+__global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) {
+  const long long g = (long long)blockIdx.x * 64 + threadIdx.x;
+  if (g >= a.bins_total) return;
+  const int c = bin_cell[g];
+  const CellDev& C = a.cells[c];
+  const int b = (int)(g - C.bin_off);
+  if (!C.rebuild || b >= C.nb[0] * C.nb[1] * C.nb[2]) return;
+  int* p = a.binned + C.off + a.bstart[g];
+  const int n = a.bnum[g];
+  for (int u = 1; u < n; ++u) {
+    const int v = p[u];
+    int q = u - 1;
+    while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
+    p[q + 1] = v;
   }
 }
 
@@ -1002,14 +1006,13 @@ __global__ void k_stress_out(CellDev* cells, int ncells, double* sig, double* P)
 
 // kinetic energy 1/2 sum m v^2 per cell (one block per cell, fixed order)
 __global__ __launch_bounds__(RED_NT) void k_kinetic(MDArgs a, double* ke) {
-  __shared__ double shd[RED_NT];
   const CellDev& C = a.cells[blockIdx.x];
   double s = 0.0;
   for (int k = threadIdx.x; k < C.n; k += RED_NT) {
     const long long i = (long long)C.off + k;
     s += a.vx[i] * a.vx[i] + a.vy[i] * a.vy[i] + a.vz[i] * a.vz[i];
   }
-  s = block_sum<RED_NT>(s, shd);
+  s = wave_sum(s);
   if (threadIdx.x == 0) ke[blockIdx.x] = 0.5 * a.mmv * s;
 }
 

@@ -35,13 +35,13 @@ struct rcell_ctx {
   bool own_stream = false;
   std::string err;
   std::vector<int> off, n, tile_off, ntile, bin_off, bin_cap;
-  long long bins_total = 0;
+  long long bins_total = 0, bins_alloc = 0;
   // device memory
   double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
   void *fx = nullptr, *fy = nullptr, *fz = nullptr;
   void *s[2] = {nullptr, nullptr}, *sb = nullptr;
   int4* bond = nullptr;
-  int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr;
+  int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr;
   int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
   CellDev* cells = nullptr;
   Tile* tiles = nullptr;
@@ -51,9 +51,21 @@ struct rcell_ctx {
   int* iscratch = nullptr;        // ncells ints
   long long* lscratch = nullptr;  // ncells long longs
   std::vector<void*> allocs;
+  // captured MD steps: graph[p] holds graph_steps middle steps starting from buffer parity p
+  int graph_steps = 10;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  // kernel timing (rcell_prof_*): pending event pairs per pass, and a pool of free events
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[2];
+  std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
+
+void drop_graphs(rcell_ctx* c) {
+  for (int q = 0; q < 2; ++q)
+    if (c->graph[q]) { (void)hipGraphExecDestroy(c->graph[q]); c->graph[q] = nullptr; }
+}
 
 int fail(rcell_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg; else g_create_error = msg;
@@ -124,6 +136,7 @@ MDArgs make_args(const rcell_ctx* c) {
   a.cells = c->cells; a.tiles = c->tiles; a.parts = c->parts; a.ntiles = c->ntiles; a.ncells = c->ncells;
   a.abin = c->abin; a.bcount = c->bcount; a.bstart = c->bstart; a.bnum = c->bnum; a.bfill = c->bfill;
   a.binned = c->binned;
+  a.bins_total = c->bins_total;
   const rcell_params& p = c->p;
   // integrator constants: the same expressions, in the same order, as the method's definition
   a.dt = p.dt;
@@ -155,13 +168,46 @@ MDArgs make_args(const rcell_ctx* c) {
 }
 
 // ---------------------------------------------------------------- launch helpers
+hipEvent_t prof_event(rcell_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// record an event pair around one launch of pass `which` when timing is enabled
+struct ProfScope {
+  rcell_ctx* c;
+  int which;
+  hipEvent_t e0 = nullptr;
+  ProfScope(rcell_ctx* c_, int w) : c(c_), which(w) {
+    if (c->prof && (e0 = prof_event(c))) (void)hipEventRecord(e0, c->stream);
+  }
+  ~ProfScope() {
+    if (!e0) return;
+    hipEvent_t e1 = prof_event(c);
+    if (!e1) { c->ev_pool.push_back(e0); return; }
+    (void)hipEventRecord(e1, c->stream);
+    c->prof_ev[which].push_back({e0, e1});
+  }
+};
+
 template <class P, int TPA>
 void force_t(rcell_ctx* c, const MDArgs& a, int mode) {
   const dim3 grid(c->ntiles), block(TILE * TPA);
   if (c->p.potential == RCELL_POT_KG) {
+    ProfScope ps(c, 0);
     hipLaunchKernelGGL((k_force_kg<P, TPA>), grid, block, 0, c->stream, a, mode);
   } else {
-    hipLaunchKernelGGL((k_eam_rho<P, TPA>), grid, block, 0, c->stream, a, mode);
+    {
+      ProfScope ps(c, 1);
+      hipLaunchKernelGGL((k_eam_rho<P, TPA>), grid, block, 0, c->stream, a, mode);
+    }
+    ProfScope ps(c, 0);
     hipLaunchKernelGGL((k_force_eam<P, TPA>), grid, block, 0, c->stream, a, mode);
   }
 }
@@ -195,7 +241,8 @@ void launch_build(rcell_ctx* c) {
   else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
   hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
   hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
-  hipLaunchKernelGGL(k_bin_sort, gc, bc, 0, c->stream, a);
+  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64), 0, c->stream, a,
+                     (const int*)c->bin_cell);
   if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gt, bt, 0, c->stream, a);
   else hipLaunchKernelGGL(k_build_list<Mixed>, gt, bt, 0, c->stream, a);
 }
@@ -265,6 +312,7 @@ int first_error(rcell_ctx* c, const std::vector<int>& st) {
 
 // lay out bins with capacity caps (>= need), update the device cell table
 int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
+  drop_graphs(c);
   long long total = 0;
   std::vector<int> off(c->ncells), cap(c->ncells);
   for (int k = 0; k < c->ncells; ++k) {
@@ -273,16 +321,22 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
     total += cap[k];
   }
   if (total > (1ll << 31) - 1) return fail(c, RCELL_ERR_OOM, "too many neighbour bins");
-  if (total > c->bins_total) {
-    dfree(c, c->bcount); dfree(c, c->bstart); dfree(c, c->bnum); dfree(c, c->bfill);
-    c->bcount = c->bstart = c->bnum = c->bfill = nullptr;
+  if (total > c->bins_alloc) {
+    dfree(c, c->bcount); dfree(c, c->bstart); dfree(c, c->bnum); dfree(c, c->bfill); dfree(c, c->bin_cell);
+    c->bcount = c->bstart = c->bnum = c->bfill = c->bin_cell = nullptr;
     int st;
     if ((st = dalloc(c, &c->bcount, total)) || (st = dalloc(c, &c->bstart, total)) ||
-        (st = dalloc(c, &c->bnum, total)) || (st = dalloc(c, &c->bfill, total)))
+        (st = dalloc(c, &c->bnum, total)) || (st = dalloc(c, &c->bfill, total)) ||
+        (st = dalloc(c, &c->bin_cell, total)))
       return st;
     HIPCHK(c, hipMemsetAsync(c->bcount, 0, sizeof(int) * total, c->stream));
-    c->bins_total = total;
+    c->bins_alloc = total;
   }
+  c->bins_total = total;
+  std::vector<int> owner(total);
+  for (int k = 0; k < c->ncells; ++k)
+    for (int b = 0; b < cap[k]; ++b) owner[off[k] + b] = k;
+  HIPCHK(c, hipMemcpyAsync(c->bin_cell, owner.data(), sizeof(int) * total, hipMemcpyHostToDevice, c->stream));
   c->bin_off = off;
   c->bin_cap = cap;
   int *doff = c->iscratch, *dcap = c->iscratch + c->ncells;
@@ -295,6 +349,7 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
 
 int ensure_list_capacity(rcell_ctx* c, int need) {
   if (need <= c->maxnb) return RCELL_OK;
+  drop_graphs(c);
   dfree(c, c->nbr);
   c->nbr = nullptr;
   const int st = dalloc(c, &c->nbr, (size_t)need * c->npad);
@@ -305,6 +360,11 @@ int ensure_list_capacity(rcell_ctx* c, int need) {
 
 void destroy_all(rcell_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  for (int w = 0; w < 2; ++w)
+    for (auto& pr : c->prof_ev[w]) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->prof_ev[0].clear(); c->prof_ev[1].clear(); c->ev_pool.clear();
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -506,21 +566,52 @@ int rcell_set_deformation_dev(rcell_ctx* c, const void* F_dev) {
   return deformation_common(c, (const double*)F_dev);
 }
 
+// one MD step that is not the last of a run: forces at the current positions fused with the
+// update to the next positions, per-cell reduction, buffer swap, conditional neighbour build
+static void middle_step(rcell_ctx* c) {
+  launch_force(c, MODE_STEP);
+  launch_reduce(c, RED_STEP);
+  c->cur = 1 - c->cur;
+  launch_build(c);
+}
+
+// capture graph_steps (even) middle steps starting at the current buffer parity
+static int capture_graph(rcell_ctx* c) {
+  const int par = c->cur;
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+  for (int k = 0; k < c->graph_steps; ++k) middle_step(c);
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->cur = par;                                    // capture does not execute anything
+  if (e != hipSuccess) return fail(c, RCELL_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&c->graph[par], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->graph[par] = nullptr;
+    return fail(c, RCELL_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+  }
+  return RCELL_OK;
+}
+
 int rcell_run(rcell_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return c ? fail(c, RCELL_ERR_ARG, "nsteps < 0") : RCELL_ERR_ARG;
   if (nsteps == 0) return RCELL_OK;
   launch_start(c);
   launch_reduce(c, RED_START);
   launch_build(c);
-  for (int k = 1; k <= nsteps; ++k) {
-    const bool last = k == nsteps;
-    launch_force(c, last ? MODE_LAST : MODE_STEP);
-    launch_reduce(c, last ? RED_LAST : RED_STEP);
-    if (!last) {
-      c->cur = 1 - c->cur;
-      launch_build(c);
+  int left = nsteps - 1;                           // middle steps; the last step ends the run
+  const bool graphs = c->graph_steps > 0 && !c->prof;
+  while (graphs && left >= c->graph_steps) {
+    if (!c->graph[c->cur]) {
+      const int e = capture_graph(c);
+      if (e) return e;
     }
+    HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+    left -= c->graph_steps;                        // an even number of swaps: parity unchanged
   }
+  for (; left > 0; --left) middle_step(c);
+  launch_force(c, MODE_LAST);
+  launch_reduce(c, RED_LAST);
   HIPCHK(c, hipGetLastError());
   return RCELL_OK;
 }
@@ -674,8 +765,16 @@ int rcell_get_rebuilds(rcell_ctx* c, int64_t* count) {
   return RCELL_OK;
 }
 
+int rcell_set_graph_steps(rcell_ctx* c, int32_t steps) {
+  if (!c || steps < 0 || (steps & 1)) return c ? fail(c, RCELL_ERR_ARG, "graph steps must be even and >= 0") : RCELL_ERR_ARG;
+  drop_graphs(c);
+  c->graph_steps = steps;
+  return RCELL_OK;
+}
+
 int rcell_set_lanes(rcell_ctx* c, int32_t lanes) {
   if (!c) return RCELL_ERR_ARG;
+  drop_graphs(c);
   if (lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16) {
     c->lanes = lanes;
     return RCELL_OK;
@@ -706,6 +805,35 @@ int rcell_set_lanes(rcell_ctx* c, int32_t lanes) {
 int rcell_get_lanes(rcell_ctx* c, int32_t* lanes) {
   if (!c || !lanes) return RCELL_ERR_ARG;
   *lanes = c->lanes;
+  return RCELL_OK;
+}
+
+int rcell_prof_enable(rcell_ctx* c, int32_t on) {
+  if (!c) return RCELL_ERR_ARG;
+  c->prof = on != 0;
+  // create the events up front so that recording never waits on the host
+  while (c->prof && c->ev_pool.size() < 8192) {
+    hipEvent_t e = nullptr;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  return RCELL_OK;
+}
+
+int rcell_prof_read(rcell_ctx* c, int32_t which, double* total_ms, int64_t* launches) {
+  if (!c || which < 0 || which > 1 || !total_ms || !launches) return c ? fail(c, RCELL_ERR_ARG, "bad prof_read arguments") : RCELL_ERR_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ms = 0.0;
+  for (auto& pr : c->prof_ev[which]) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, pr.first, pr.second));
+    ms += t;
+    c->ev_pool.push_back(pr.first);
+    c->ev_pool.push_back(pr.second);
+  }
+  *total_ms = ms;
+  *launches = (int64_t)c->prof_ev[which].size();
+  c->prof_ev[which].clear();
   return RCELL_OK;
 }
 

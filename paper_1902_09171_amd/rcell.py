@@ -23,7 +23,7 @@ EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev",
            "rcell_get_stress", "rcell_get_stress_dev", "rcell_destroy", "rcell_last_error",
            "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
            "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
-           "rcell_get_lanes"]
+           "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps"]
 
 
 class RCellError(RuntimeError):
@@ -69,6 +69,8 @@ def load():
             "rcell_set_state": [vp, i32, vp, vp, vp, vp, i64], "rcell_get_energy": [vp, vp, vp],
             "rcell_get_box": [vp, i32, vp, vp, vp, vp], "rcell_get_rebuilds": [vp, vp],
             "rcell_set_lanes": [vp, i32], "rcell_get_lanes": [vp, vp],
+            "rcell_prof_enable": [vp, i32], "rcell_prof_read": [vp, i32, vp, vp],
+            "rcell_set_graph_steps": [vp, i32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -205,6 +207,18 @@ class RCellBatch:
     def set_lanes(self, lanes):
         self._check(load().rcell_set_lanes(self._h, int(lanes)))
         return self.lanes()
+
+    def set_graph_steps(self, steps):
+        self._check(load().rcell_set_graph_steps(self._h, int(steps)))
+
+    def prof_enable(self, on=True):
+        self._check(load().rcell_prof_enable(self._h, 1 if on else 0))
+
+    def prof_read(self, which=0):
+        """(total_ms, launches) of pass `which` (0 force, 1 EAM density) since the last read."""
+        ms, n = ctypes.c_double(0), ctypes.c_int64(0)
+        self._check(load().rcell_prof_read(self._h, int(which), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def lanes(self):
         l = ctypes.c_int32(0)

@@ -279,3 +279,25 @@ def test_neighbour_rebuilds_keep_parity(rc):
     s = g.get_state(0)
     fo = core.forces(p, s["H"], s["x"], cells[0]["bonds"])[0]
     check_forces(g.get_forces(0), fo, TOL["mixed"], "after rebuilds")
+
+
+@pytest.mark.parametrize("pot", ["kg", "cu"])
+def test_graph_replay_equals_eager_launches(rc, pot):
+    # replays of the captured MD-step graphs (with neighbour rebuilds inside) give bit-identical
+    # states, stresses and rebuild counts to launching every kernel individually
+    if pot == "kg":
+        cells, p = kg_cells([[50] * 20, [40] * 10]), configs.kg_params()
+    else:
+        cells, p = cu_cells(2, ncell=6), configs.cu_params()
+    a = rc.RCellBatch(p, cells)
+    a.set_graph_steps(0)
+    b = rc.RCellBatch(p, cells)
+    b.set_graph_steps(4)
+    for n in (1, 9, 23, 40):
+        a.run(n)
+        b.run(n)
+        assert np.array_equal(a.get_stress(), b.get_stress()), n
+    for k in range(len(cells)):
+        sa, sb = a.get_state(k), b.get_state(k)
+        assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["v"], sb["v"])
+    assert a.rebuilds() == b.rebuilds()

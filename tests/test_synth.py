@@ -12,13 +12,13 @@ def test_kg_melt_shape_density_bonds():
     assert x.min() >= 0 and x.max() < L
     d = x[b[:, 1]] - x[b[:, 0]]
     d -= L * np.rint(d / L)
-    assert np.allclose(np.linalg.norm(d, axis=1), 0.97, atol=1e-12)
-    # soft excluded volume: almost all beads keep their nearest neighbour beyond 0.8 sigma
+    assert np.allclose(np.linalg.norm(d, axis=1), 0.97, atol=1e-3)
+    # soft excluded volume plus geometric relaxation: no two beads closer than 0.8 sigma
     dd = x[:, None] - x[None]
     dd -= L * np.rint(dd / L)
     r = np.linalg.norm(dd, axis=-1)
     np.fill_diagonal(r, 9)
-    assert (r.min(1) > 0.8).mean() > 0.95 and r.min() > 0.6
+    assert r.min() > 0.8
     x2, _, _ = kg_melt([50] * 20, seed=1)
     assert np.array_equal(x, x2)
 
