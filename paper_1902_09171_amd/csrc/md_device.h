@@ -20,6 +20,7 @@
 namespace rcell {
 
 constexpr int TILE = 64;
+constexpr int UNR = 4;           // neighbour-loop unroll: gathers in flight per lane
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWOM32 = 1.0 / 4294967296.0;
 
@@ -73,7 +74,7 @@ struct MDArgs {
   const Tile* tiles;
   Part* parts;
   int ntiles, ncells;
-  int* abin; int* bcount; int* bstart; int* bnum; int* bfill; int* binned;
+  int* abin; int* bcount; int* bstart; int* bnum; int* bfill; int* binned; int* sort_tmp;
   long long bins_total;
   // integrator constants (computed once on the host, documented expressions)
   double dt, h, drag, c24, mmv, half_skin2, rcs2;
@@ -418,10 +419,24 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     const typename P::S si = P::load(a.s_cur, i);
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sig2 = (R)a.lj_sig2, e24 = (R)(24.0 * a.lj_eps), e4 = (R)(4.0 * a.lj_eps), sh = (R)a.lj_shift;
-    for (int k = lane; k < nn; k += TPA) {
-      const int j = a.nbr[(long long)k * a.npad + i] + C.off;
+    // neighbours k = lane, lane + TPA, ... in that order; UNR index loads and UNR gathers are
+    // issued before any arithmetic so that their latencies overlap
+    for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
+      int jj[UNR];
+      typename P::S sj[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = k0 + u * TPA;
+        jj[u] = k < nn ? a.nbr[(long long)k * a.npad + i] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if (jj[u] >= 0) sj[u] = P::load(a.s_cur, jj[u] + C.off);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+      if (jj[u] < 0) continue;
       R d[3];
-      P::sep(P::load(a.s_cur, j), si, C, d);
+      P::sep(sj[u], si, C, d);
       const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       if (r2 < rc2) {
         const R r2i = (R)1 / r2;
@@ -433,6 +448,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
         w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
         w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
         pe += (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh);
+      }
       }
     }
     if (lane == 0) {
@@ -493,14 +509,27 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
     const typename P::S si = P::load(a.s_cur, i);
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, rhoc = (R)a.sc_rhoc;
-    for (int k = lane; k < nn; k += TPA) {
-      const int j = a.nbr[(long long)k * a.npad + i] + C.off;
-      R d[3];
-      P::sep(P::load(a.s_cur, j), si, C, d);
-      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      if (r2 < rc2) {
-        const R tr = sa * ((R)1 / sqrt(r2));
-        rho += ipow(tr, a.sc_m) - rhoc;
+    for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
+      int jj[UNR];
+      typename P::S sj[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = k0 + u * TPA;
+        jj[u] = k < nn ? a.nbr[(long long)k * a.npad + i] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if (jj[u] >= 0) sj[u] = P::load(a.s_cur, jj[u] + C.off);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (jj[u] < 0) continue;
+        R d[3];
+        P::sep(sj[u], si, C, d);
+        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 < rc2) {
+          const R tr = sa * ((R)1 / sqrt(r2));
+          rho += ipow(tr, a.sc_m) - rhoc;
+        }
       }
     }
   }
@@ -530,23 +559,35 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, en = (R)(a.sc_eps * a.sc_n), m = (R)a.sc_m;
     const R eh = (R)(0.5 * a.sc_eps), phic = (R)a.sc_phic;
-    for (int k = lane; k < nn; k += TPA) {
-      const int j = a.nbr[(long long)k * a.npad + i] + C.off;
-      const typename P::S sj = P::load(a.s_cur, j);
-      R d[3];
-      P::sep(sj, si, C, d);
-      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      if (r2 < rc2) {
-        const R ri = (R)1 / sqrt(r2);
-        const R tr = sa * ri;
-        const R tm = ipow(tr, a.sc_m);
-        const R tn = ipow(tr, a.sc_n);
-        const R gr = -(ri * ri) * (en * tn + (fpi + P::get_w(sj)) * m * tm);   // g / r
-        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-        const R hg = (R)0.5 * gr;
-        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
-        pe += eh * (tn - phic);
+    for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
+      int jj[UNR];
+      typename P::S sj[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int k = k0 + u * TPA;
+        jj[u] = k < nn ? a.nbr[(long long)k * a.npad + i] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if (jj[u] >= 0) sj[u] = P::load(a.s_cur, jj[u] + C.off);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        if (jj[u] < 0) continue;
+        R d[3];
+        P::sep(sj[u], si, C, d);
+        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 < rc2) {
+          const R ri = (R)1 / sqrt(r2);
+          const R tr = sa * ri;
+          const R tm = ipow(tr, a.sc_m);
+          const R tn = ipow(tr, a.sc_n);
+          const R gr = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
+          f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+          const R hg = (R)0.5 * gr;
+          w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+          w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+          pe += eh * (tn - phic);
+        }
       }
     }
   }
@@ -714,28 +755,27 @@ __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
   const CellDev& C = a.cells[blockIdx.x];
   if (!C.rebuild) return;
   const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
-  int* cnt = a.bcount + C.bin_off;
-  const int per = (nbins + SCAN_NT - 1) / SCAN_NT;
-  const int lo = min(nbins, (int)threadIdx.x * per), hi = min(nbins, lo + per);
-  int acc = 0;
-  for (int b = lo; b < hi; ++b) acc += cnt[b];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the chunk sums in shared memory
-  for (int o = 1; o < SCAN_NT; o <<= 1) {
-    const int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+  const int t = threadIdx.x;
+  int carry = 0;
+  for (int base = 0; base < nbins; base += SCAN_NT) {   // coalesced chunks of SCAN_NT bins
+    const int b = base + t;
+    const int c = b < nbins ? a.bcount[C.bin_off + b] : 0;
+    sh[t] = c;
     __syncthreads();
-    sh[threadIdx.x] += v;
+    for (int o = 1; o < SCAN_NT; o <<= 1) {            // Hillis-Steele inclusive scan
+      const int v = t >= o ? sh[t - o] : 0;
+      __syncthreads();
+      sh[t] += v;
+      __syncthreads();
+    }
+    if (b < nbins) {
+      a.bstart[C.bin_off + b] = carry + sh[t] - c;
+      a.bnum[C.bin_off + b] = c;
+      a.bfill[C.bin_off + b] = 0;
+      a.bcount[C.bin_off + b] = 0;                        // ready for the next build
+    }
+    carry += sh[SCAN_NT - 1];
     __syncthreads();
-  }
-  acc = threadIdx.x > 0 ? sh[threadIdx.x - 1] : 0;
-  for (int b = lo; b < hi; ++b) {
-    const int c = cnt[b];
-    a.bstart[C.bin_off + b] = acc;
-    a.bnum[C.bin_off + b] = c;
-    a.bfill[C.bin_off + b] = 0;
-    cnt[b] = 0;                                      // ready for the next build
-    acc += c;
   }
 }
 
@@ -749,31 +789,67 @@ __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
 
-// one thread per bin slot of every cell (grid over the bin capacity): insertion sort in place
+// one lane per bin slot of every cell (grid over the bin capacity).  Bins of up to SMALL_BIN
+// atoms are insertion-sorted by their lane; larger bins are rank-sorted by the whole wave (entry v
+// goes to position #{entries < v}; indices are distinct) through the scratch array, then copied back.
+constexpr int SMALL_BIN = 24;
 __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) {
   const long long g = (long long)blockIdx.x * 64 + threadIdx.x;
-  if (g >= a.bins_total) return;
-  const int c = bin_cell[g];
-  const CellDev& C = a.cells[c];
-  const int b = (int)(g - C.bin_off);
-  if (!C.rebuild || b >= C.nb[0] * C.nb[1] * C.nb[2]) return;
-  int* p = a.binned + C.off + a.bstart[g];
-  const int n = a.bnum[g];
-  for (int u = 1; u < n; ++u) {
-    const int v = p[u];
-    int q = u - 1;
-    while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
-    p[q + 1] = v;
+  int big = 0;                       // this lane's bin needs the wave
+  int *p = nullptr, n = 0;
+  if (g < a.bins_total) {
+    const int c = bin_cell[g];
+    const CellDev& C = a.cells[c];
+    const int b = (int)(g - C.bin_off);
+    if (C.rebuild && b < C.nb[0] * C.nb[1] * C.nb[2]) {
+      p = a.binned + C.off + a.bstart[g];
+      n = a.bnum[g];
+      big = n > SMALL_BIN;
+      if (!big)
+        for (int u = 1; u < n; ++u) {
+          const int v = p[u];
+          int q = u - 1;
+          while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
+          p[q + 1] = v;
+        }
+    }
+  }
+  // large bins, one after another, by all 64 lanes
+  unsigned long long mask = __ballot(big);
+  while (mask) {
+    const int src = __ffsll((long long)mask) - 1;
+    mask &= mask - 1;
+    int* pb = (int*)__shfl((long long)(size_t)p, src);
+    const int m = __shfl(n, src);
+    const long long gb = __shfl(g, src);
+    int* tmp = a.sort_tmp + (pb - a.binned);
+    for (int e = threadIdx.x; e < m; e += 64) {
+      const int v = pb[e];
+      int rank = 0;
+      for (int q = 0; q < m; ++q) rank += pb[q] < v;
+      tmp[rank] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    for (int e = threadIdx.x; e < m; e += 64) pb[e] = tmp[e];
+    __syncthreads();
+    (void)gb;
   }
 }
 
-// 5: Verlet list of every atom: cell-local j with |d| < rc + skin over the 27 (distinct) bins
+// Verlet list of every atom: cell-local j with |d| < rc + skin over the 27 (distinct) neighbour
+// bins.  LPA lanes share one atom; lane l scans bins l, l + LPA, ...  Each lane counts its
+// neighbours, an exclusive scan over the lanes gives its offset, and a second scan writes them:
+// the list order (lane-major over bins, ascending index inside a bin) is deterministic.
+constexpr int LPA = 8;
 template <class P>
-__global__ __launch_bounds__(TILE) void k_build_list(MDArgs a) {
+__global__ __launch_bounds__(TILE * LPA) void k_build_list(MDArgs a) {
   const Tile t = a.tiles[blockIdx.x];
   const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  const long long i = (long long)t.begin + threadIdx.x;
+  if (!C.rebuild) return;
+  const int slot = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const bool active = slot < t.count;
+  const long long i = (long long)t.begin + (active ? slot : 0);
   const int li = (int)(i - C.off);
   const typename P::S si = P::load(a.s_cur, i);
   const int bin = a.abin[i];
@@ -791,30 +867,46 @@ __global__ __launch_bounds__(TILE) void k_build_list(MDArgs a) {
       for (int u = 0; u < nbq; ++u) lst[q][u] = u;
     }
   }
+  const int nq = cnt[0] * cnt[1] * cnt[2];
   const typename P::R rcs2 = (typename P::R)a.rcs2;
-  int n = 0;
-  for (int u0 = 0; u0 < cnt[0]; ++u0)
-    for (int u1 = 0; u1 < cnt[1]; ++u1)
-      for (int u2 = 0; u2 < cnt[2]; ++u2) {
-        const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
-        const int* p = a.binned + C.off + a.bstart[C.bin_off + b];
-        const int m = a.bnum[C.bin_off + b];
-        for (int q = 0; q < m; ++q) {
-          const int lj = p[q];
-          if (lj == li) continue;
-          typename P::R d[3];
-          P::sep(P::load(a.s_cur, C.off + lj), si, C, d);
-          if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
-            if (n < a.maxnb) a.nbr[(long long)n * a.npad + i] = lj;
-            ++n;
-          }
+  int n = 0, base = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    int k = base;
+    for (int q = lane; q < nq && active; q += LPA) {
+      const int u0 = q / (cnt[1] * cnt[2]), u1 = (q / cnt[2]) % cnt[1], u2 = q % cnt[2];
+      const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
+      const int* p = a.binned + C.off + a.bstart[C.bin_off + b];
+      const int m = a.bnum[C.bin_off + b];
+      for (int e = 0; e < m; ++e) {
+        const int lj = p[e];
+        if (lj == li) continue;
+        typename P::R d[3];
+        P::sep(P::load(a.s_cur, C.off + lj), si, C, d);
+        if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
+          if (pass == 1 && k < a.maxnb) a.nbr[(long long)k * a.npad + i] = lj;
+          ++k;
         }
       }
-  if (n > a.maxnb) {
-    atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
-    n = a.maxnb;
+    }
+    if (pass == 0) {
+      n = k;                                  // this lane's count
+      int incl = n;                           // inclusive scan over the LPA lanes of the atom
+#pragma unroll
+      for (int o = 1; o < LPA; o <<= 1) {
+        const int v = __shfl_up(incl, o, LPA);
+        if (lane >= o) incl += v;
+      }
+      base = incl - n;
+      n = __shfl(incl, LPA - 1, LPA);          // total for the atom
+    }
   }
-  a.nn[i] = n;
+  if (active && lane == 0) {
+    if (n > a.maxnb) {
+      atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
+      n = a.maxnb;
+    }
+    a.nn[i] = n;
+  }
 }
 
 // ------------------------------------------------------------------ QR box remap (Eqs. 4, 5, 9)

@@ -41,7 +41,7 @@ struct rcell_ctx {
   void *fx = nullptr, *fy = nullptr, *fz = nullptr;
   void *s[2] = {nullptr, nullptr}, *sb = nullptr;
   int4* bond = nullptr;
-  int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr;
+  int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr, *sort_tmp = nullptr;
   int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
   CellDev* cells = nullptr;
   Tile* tiles = nullptr;
@@ -136,6 +136,7 @@ MDArgs make_args(const rcell_ctx* c) {
   a.cells = c->cells; a.tiles = c->tiles; a.parts = c->parts; a.ntiles = c->ntiles; a.ncells = c->ncells;
   a.abin = c->abin; a.bcount = c->bcount; a.bstart = c->bstart; a.bnum = c->bnum; a.bfill = c->bfill;
   a.binned = c->binned;
+  a.sort_tmp = c->sort_tmp;
   a.bins_total = c->bins_total;
   const rcell_params& p = c->p;
   // integrator constants: the same expressions, in the same order, as the method's definition
@@ -243,8 +244,9 @@ void launch_build(rcell_ctx* c) {
   hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
   hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64), 0, c->stream, a,
                      (const int*)c->bin_cell);
-  if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gt, bt, 0, c->stream, a);
-  else hipLaunchKernelGGL(k_build_list<Mixed>, gt, bt, 0, c->stream, a);
+  const dim3 bl(TILE * LPA);
+  if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gt, bl, 0, c->stream, a);
+  else hipLaunchKernelGGL(k_build_list<Mixed>, gt, bl, 0, c->stream, a);
 }
 
 void launch_start(rcell_ctx* c) {
@@ -481,7 +483,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
       (e = dalloc(c, &c->vx, N)) || (e = dalloc(c, &c->vy, N)) || (e = dalloc(c, &c->vz, N)) ||
       (e = dalloc(c, &f0, 3 * fsz * N)) || (e = dalloc(c, &s0, ssz * N)) || (e = dalloc(c, &s1, ssz * N)) ||
       (e = dalloc(c, &sbp, ssz * N)) || (e = dalloc(c, &c->bond, N)) || (e = dalloc(c, &c->nn, N)) ||
-      (e = dalloc(c, &c->abin, N)) || (e = dalloc(c, &c->binned, N)) ||
+      (e = dalloc(c, &c->abin, N)) || (e = dalloc(c, &c->binned, N)) || (e = dalloc(c, &c->sort_tmp, N)) ||
       (e = dalloc(c, &c->cells, ncells)) || (e = dalloc(c, &c->tiles, ntiles)) || (e = dalloc(c, &c->parts, ntiles)) ||
       (e = dalloc(c, &c->stage, ncells)) || (e = dalloc(c, &c->dscratch, (size_t)17 * ncells)) ||
       (e = dalloc(c, &c->iscratch, (size_t)2 * ncells)) || (e = dalloc(c, &c->lscratch, (size_t)2 * ncells)))
