@@ -40,9 +40,10 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_binding_lists_match_header():
-    from paper_1902_09171_amd import rcell
+    from paper_1902_09171_amd import rcell, rsur
     decl = [n for n in declared() if n.startswith("rcell_")]
     assert sorted(rcell.EXPORTS) == decl
+    assert sorted(rsur.EXPORTS) == [n for n in declared() if n.startswith("rsur_")]
 
 
 def test_create_rejects_bad_arguments_without_touching_the_gpu(lib):
