@@ -78,8 +78,8 @@ def main():
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described "
-                                   "in DESIGN.md and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the r-cell library runs on one GPU; sharding the cells "
+                                   "over several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

@@ -109,6 +109,10 @@ int rcell_run(rcell_ctx* ctx, int32_t nsteps);
  * per-cell error status if any (RCELL_ERR_NONFINITE for a non-finite stress). */
 int rcell_get_stress(rcell_ctx* ctx, double* sigma, double* P);
 
+/* As rcell_get_stress, and also the window-averaged stress in the MD frame (before the rotation of
+ * Eq. 7) into sigma_md (ncells*6 host doubles, or NULL).  Clears the window once. */
+int rcell_get_stress_ext(rcell_ctx* ctx, double* sigma, double* P, double* sigma_md);
+
 /* As rcell_get_stress, writing ncells*6 (and ncells*9, if P_dev is not NULL) doubles to
  * caller-owned device memory, enqueued on the context's stream; does not synchronise. */
 int rcell_get_stress_dev(rcell_ctx* ctx, void* sigma_dev, void* P_dev);
@@ -151,6 +155,17 @@ int rcell_set_graph_steps(rcell_ctx* ctx, int32_t steps);
  * milliseconds and the number of launches since the last read, and resets both. */
 int rcell_prof_enable(rcell_ctx* ctx, int32_t on);
 int rcell_prof_read(rcell_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);
+
+/* ---- stateless coupling utilities (no context; enqueued on hip_stream, NULL = null stream) ---- */
+/* Eq. (4) for n deformation gradients in device memory (n*9 doubles, row-major): Q and R (n*9
+ * doubles each, device) by the same Gram-Schmidt as rcell_set_deformation; status_dev (n int32,
+ * device, or NULL) receives 0 or RCELL_ERR_BAD_F per F (Q, R zero for a bad F). */
+int rcell_qr_dev(const void* F_dev, int32_t n, void* Q_dev, void* R_dev, void* status_dev, void* hip_stream);
+/* Eqs. (7), (8) for n MD-frame stresses (n*6 Voigt doubles, device) and their F (n*9, device):
+ * sigma_FEM = Q sigma_MD Q^T (n*6) and, if P_dev is not NULL, P = J sigma_FEM F^-T (n*9); NaN
+ * for a bad F.  Used by the surrogate path, whose stresses come from the network. */
+int rcell_stress_return_dev(const void* F_dev, const void* sigma_md_dev, int32_t n, void* sigma_fem_dev, void* P_dev,
+                            void* hip_stream);
 
 #ifdef __cplusplus
 }

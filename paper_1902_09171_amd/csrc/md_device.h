@@ -1061,12 +1061,14 @@ __global__ void k_set_box(CellDev* cells, int first, int count, double rcs) {
 }
 
 // ------------------------------------------------------------------ stress return (Eqs. 7, 8)
-__global__ void k_stress_out(CellDev* cells, int ncells, double* sig, double* P) {
+__global__ void k_stress_out(CellDev* cells, int ncells, double* sig, double* P, double* smd) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   CellDev& C = cells[c];
   double sv[6];
   for (int q = 0; q < 6; ++q) sv[q] = C.wcount > 0 ? C.wsum[q] / (double)C.wcount : C.last[q];
+  if (smd)
+    for (int q = 0; q < 6; ++q) smd[6 * c + q] = sv[q];
   const double s[9] = {sv[0], sv[3], sv[4], sv[3], sv[1], sv[5], sv[4], sv[5], sv[2]};
   double Qt[9], T[9], Sf[9];
   for (int r = 0; r < 3; ++r)
@@ -1106,6 +1108,51 @@ __global__ __launch_bounds__(RED_NT) void k_kinetic(MDArgs a, double* ke) {
   }
   s = wave_sum(s);
   if (threadIdx.x == 0) ke[blockIdx.x] = 0.5 * a.mmv * s;
+}
+
+// Eq. (4) for a batch of deformation gradients (no cell state): Q, R, status per F
+__global__ void k_qr_batch(const double* F, int n, double* Q, double* R, int* status) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double f[9], q[9], r[9];
+  for (int k = 0; k < 9; ++k) f[k] = F[9 * c + k];
+  const int st = qr_gs(f, q, r);
+  for (int k = 0; k < 9; ++k) { Q[9 * c + k] = st ? 0.0 : q[k]; R[9 * c + k] = st ? 0.0 : r[k]; }
+  if (status) status[c] = st;
+}
+
+// Eqs. (7), (8) for a batch: sigma_FEM = Q sigma_MD Q^T and P = J sigma_FEM F^-T, with Q and
+// J = prod R_ii from the QR of each F (Voigt in and out; non-finite output for a bad F)
+__global__ void k_return_batch(const double* F, const double* smd, int n, double* sfem, double* P) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double f[9], Q[9], R[9];
+  for (int k = 0; k < 9; ++k) f[k] = F[9 * c + k];
+  const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+  if (qr_gs(f, Q, R)) {
+    for (int q = 0; q < 6; ++q) sfem[6 * c + q] = __longlong_as_double(0x7ff8000000000000LL);
+    if (P) for (int q = 0; q < 9; ++q) P[9 * c + q] = __longlong_as_double(0x7ff8000000000000LL);
+    return;
+  }
+  const double* sv = smd + 6 * c;
+  const double s[9] = {sv[0], sv[3], sv[4], sv[3], sv[1], sv[5], sv[4], sv[5], sv[2]};
+  double Qt[9], T[9], Sf[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) Qt[3 * r + k] = Q[3 * k + r];
+  mat3mul(Q, s, T);
+  mat3mul(T, Qt, Sf);
+  for (int q = 0; q < 6; ++q) sfem[6 * c + q] = Sf[3 * ia[q] + ib[q]];
+  if (P) {
+    const double d = det3(f);
+    double FiT[9];
+    FiT[0] = (f[4] * f[8] - f[5] * f[7]) / d; FiT[3] = (f[2] * f[7] - f[1] * f[8]) / d; FiT[6] = (f[1] * f[5] - f[2] * f[4]) / d;
+    FiT[1] = (f[5] * f[6] - f[3] * f[8]) / d; FiT[4] = (f[0] * f[8] - f[2] * f[6]) / d; FiT[7] = (f[2] * f[3] - f[0] * f[5]) / d;
+    FiT[2] = (f[3] * f[7] - f[4] * f[6]) / d; FiT[5] = (f[1] * f[6] - f[0] * f[7]) / d; FiT[8] = (f[0] * f[4] - f[1] * f[3]) / d;
+    double Pm[9];
+    mat3mul(Sf, FiT, Pm);
+    const double J = R[0] * R[4] * R[8];
+    for (int q = 0; q < 9; ++q) P[9 * c + q] = J * Pm[q];
+  }
 }
 
 __global__ void k_set_pending(CellDev* cells, int first, int count) {

@@ -48,6 +48,7 @@ struct rcell_ctx {
   Part* parts = nullptr;
   Stage* stage = nullptr;
   double* dscratch = nullptr;     // ncells * 17 doubles: F / sigma + P / kinetic, then pe
+  double* dscratch2 = nullptr;    // ncells * 6 doubles: MD-frame stress
   int* iscratch = nullptr;        // ncells ints
   long long* lscratch = nullptr;  // ncells long longs
   std::vector<void*> allocs;
@@ -485,7 +486,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
       (e = dalloc(c, &sbp, ssz * N)) || (e = dalloc(c, &c->bond, N)) || (e = dalloc(c, &c->nn, N)) ||
       (e = dalloc(c, &c->abin, N)) || (e = dalloc(c, &c->binned, N)) || (e = dalloc(c, &c->sort_tmp, N)) ||
       (e = dalloc(c, &c->cells, ncells)) || (e = dalloc(c, &c->tiles, ntiles)) || (e = dalloc(c, &c->parts, ntiles)) ||
-      (e = dalloc(c, &c->stage, ncells)) || (e = dalloc(c, &c->dscratch, (size_t)17 * ncells)) ||
+      (e = dalloc(c, &c->stage, ncells)) || (e = dalloc(c, &c->dscratch, (size_t)17 * ncells)) || (e = dalloc(c, &c->dscratch2, (size_t)6 * ncells)) ||
       (e = dalloc(c, &c->iscratch, (size_t)2 * ncells)) || (e = dalloc(c, &c->lscratch, (size_t)2 * ncells)))
     return bail(e);
   c->fx = f0; c->fy = f0 + fsz * N; c->fz = f0 + 2 * fsz * N;
@@ -618,12 +619,31 @@ int rcell_run(rcell_ctx* c, int32_t nsteps) {
   return RCELL_OK;
 }
 
-int rcell_get_stress_dev(rcell_ctx* c, void* sigma_dev, void* P_dev) {
-  if (!c || !sigma_dev) return c ? fail(c, RCELL_ERR_ARG, "sigma_dev is NULL") : RCELL_ERR_ARG;
+static int stress_out(rcell_ctx* c, void* sigma_dev, void* P_dev, void* smd_dev) {
   hipLaunchKernelGGL(k_stress_out, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, c->ncells,
-                     (double*)sigma_dev, (double*)P_dev);
+                     (double*)sigma_dev, (double*)P_dev, (double*)smd_dev);
   HIPCHK(c, hipGetLastError());
   return RCELL_OK;
+}
+
+int rcell_get_stress_dev(rcell_ctx* c, void* sigma_dev, void* P_dev) {
+  if (!c || !sigma_dev) return c ? fail(c, RCELL_ERR_ARG, "sigma_dev is NULL") : RCELL_ERR_ARG;
+  return stress_out(c, sigma_dev, P_dev, nullptr);
+}
+
+int rcell_get_stress_ext(rcell_ctx* c, double* sigma, double* P, double* sigma_md) {
+  if (!c || !sigma) return c ? fail(c, RCELL_ERR_ARG, "sigma is NULL") : RCELL_ERR_ARG;
+  const int nc = c->ncells;
+  double* sd = c->dscratch;
+  double* pd = c->dscratch + 6 * nc;
+  int e = stress_out(c, sd, P ? pd : nullptr, sigma_md ? c->dscratch2 : nullptr);
+  if (e) return e;
+  HIPCHK(c, hipMemcpyAsync(sigma, sd, sizeof(double) * 6 * nc, hipMemcpyDeviceToHost, c->stream));
+  if (P) HIPCHK(c, hipMemcpyAsync(P, pd, sizeof(double) * 9 * nc, hipMemcpyDeviceToHost, c->stream));
+  if (sigma_md) HIPCHK(c, hipMemcpyAsync(sigma_md, c->dscratch2, sizeof(double) * 6 * nc, hipMemcpyDeviceToHost, c->stream));
+  Gathered g;
+  if ((e = gather(c, g))) return e;
+  return first_error(c, g.status);
 }
 
 int rcell_get_stress(rcell_ctx* c, double* sigma, double* P) {
@@ -808,6 +828,23 @@ int rcell_get_lanes(rcell_ctx* c, int32_t* lanes) {
   if (!c || !lanes) return RCELL_ERR_ARG;
   *lanes = c->lanes;
   return RCELL_OK;
+}
+
+int rcell_qr_dev(const void* F_dev, int32_t n, void* Q_dev, void* R_dev, void* status_dev, void* hip_stream) {
+  if (!F_dev || !Q_dev || !R_dev || n < 0) return RCELL_ERR_ARG;
+  if (n == 0) return RCELL_OK;
+  hipLaunchKernelGGL(k_qr_batch, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)hip_stream, (const double*)F_dev, n,
+                     (double*)Q_dev, (double*)R_dev, (int*)status_dev);
+  return hipGetLastError() == hipSuccess ? RCELL_OK : RCELL_ERR_DEVICE;
+}
+
+int rcell_stress_return_dev(const void* F_dev, const void* sigma_md_dev, int32_t n, void* sigma_fem_dev, void* P_dev,
+                            void* hip_stream) {
+  if (!F_dev || !sigma_md_dev || !sigma_fem_dev || n < 0) return RCELL_ERR_ARG;
+  if (n == 0) return RCELL_OK;
+  hipLaunchKernelGGL(k_return_batch, dim3((n + 63) / 64), dim3(64), 0, (hipStream_t)hip_stream, (const double*)F_dev,
+                     (const double*)sigma_md_dev, n, (double*)sigma_fem_dev, (double*)P_dev);
+  return hipGetLastError() == hipSuccess ? RCELL_OK : RCELL_ERR_DEVICE;
 }
 
 int rcell_prof_enable(rcell_ctx* c, int32_t on) {

@@ -1,0 +1,177 @@
+"""Host finite-element driver of the coupling (Sec. 2.2, Eqs. 10-14; Fig. 1): an explicit
+total-Lagrangian hex8 bar whose quadrature points take their first Piola-Kirchhoff stress from a
+stress provider - batched MD r-cells (rcell) or the learned surrogate.
+
+Per load step: F at every Gauss point from the nodal displacements (F = I + du/dX), P from the
+provider, internal forces f_int = sum_gp B^T P w det J0 (Eq. 12), lumped mass (Eq. 11), and a
+central-difference update of M d'' + f_int = f_ext (Eq. 10) with mass-proportional damping.
+Loading: the face x = 0 is held in x, the face x = L moves at a prescribed velocity along x, the
+lateral faces are free; two pins remove the remaining rigid-body motion.
+"""
+import numpy as np
+
+_XI = np.array([[-1, -1, -1], [1, -1, -1], [1, 1, -1], [-1, 1, -1],
+                [-1, -1, 1], [1, -1, 1], [1, 1, 1], [-1, 1, 1]], dtype=np.float64)
+_G = 1.0 / np.sqrt(3.0)
+
+
+def shape(xi):
+    """Trilinear shape functions N_a and their derivatives dN_a/dxi at natural point xi."""
+    t = 1.0 + _XI * xi[None, :]
+    N = t.prod(1) / 8.0
+    dN = np.empty((8, 3))
+    dN[:, 0] = _XI[:, 0] * t[:, 1] * t[:, 2] / 8.0
+    dN[:, 1] = _XI[:, 1] * t[:, 0] * t[:, 2] / 8.0
+    dN[:, 2] = _XI[:, 2] * t[:, 0] * t[:, 1] / 8.0
+    return N, dN
+
+
+class Hex8Bar:
+    """Structured nx x ny x nz hex8 mesh of a bar [0, Lx] x [0, Ly] x [0, Lz], 2x2x2 Gauss points.
+
+    imperfection < 1 scales the lateral coordinates of the middle cross-section about the bar axis
+    (a seed for necking)."""
+
+    def __init__(self, nel=(8, 2, 2), size=(200.0, 50.0, 50.0), rho0=0.85, imperfection=1.0):
+        nx, ny, nz = nel
+        Lx, Ly, Lz = size
+        self.nel, self.size, self.rho0 = nel, size, rho0
+        xs, ys, zs = np.linspace(0, Lx, nx + 1), np.linspace(0, Ly, ny + 1), np.linspace(0, Lz, nz + 1)
+        self.node = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
+        X = np.array([[x, y, z] for x in xs for y in ys for z in zs])
+        if imperfection != 1.0 and nx % 2 == 0:
+            mid = np.isclose(X[:, 0], xs[nx // 2])
+            X[mid, 1] = Ly / 2 + (X[mid, 1] - Ly / 2) * imperfection
+            X[mid, 2] = Lz / 2 + (X[mid, 2] - Lz / 2) * imperfection
+        self.X = X
+        self.nnodes = len(X)
+        conn = []
+        for i in range(nx):
+            for j in range(ny):
+                for k in range(nz):
+                    conn.append([self.node(i + a, j + b, k + c) for a, b, c in
+                                 ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1))])
+        self.conn = np.array(conn)
+        # per Gauss point: element, dN/dX (8 x 3), w det J0, N
+        gps = [np.array([a, b, c]) * _G for c in (-1, 1) for b in (-1, 1) for a in (-1, 1)]
+        elem, B, wdet, Ns = [], [], [], []
+        for e, nodes in enumerate(self.conn):
+            Xe = X[nodes]
+            for xi in gps:
+                N, dN = shape(xi)
+                J = Xe.T @ dN                       # J_ij = sum_a X_a,i dN_a/dxi_j
+                B.append(dN @ np.linalg.inv(J))     # dN_a/dX_j
+                wdet.append(np.linalg.det(J))       # Gauss weight 1
+                elem.append(e)
+                Ns.append(N)
+        self.gp_elem = np.array(elem)
+        self.B = np.array(B)                        # (ngp, 8, 3)
+        self.wdet = np.array(wdet)
+        self.ngp = len(self.B)
+        self.mass = np.zeros(self.nnodes)
+        for g in range(self.ngp):
+            np.add.at(self.mass, self.conn[self.gp_elem[g]], rho0 * Ns[g] * self.wdet[g])
+        self.volume = self.wdet.sum()
+
+    def deformation_gradients(self, u):
+        """F = I + sum_a u_a (x) dN_a/dX at every Gauss point, (ngp, 3, 3)."""
+        ue = u[self.conn[self.gp_elem]]             # (ngp, 8, 3)
+        return np.eye(3)[None] + np.einsum("gai,gaj->gij", ue, self.B)
+
+    def internal_forces(self, P):
+        """f_int_a = sum_gp P . dN_a/dX w det J0 (Eq. 12), (nnodes, 3)."""
+        fe = np.einsum("gij,gaj->gai", P, self.B) * self.wdet[:, None, None]
+        f = np.zeros((self.nnodes, 3))
+        np.add.at(f, self.conn[self.gp_elem].ravel(), fe.reshape(-1, 3))
+        return f
+
+    def face(self, axis, side):
+        lo, hi = self.X[:, axis].min(), self.X[:, axis].max()
+        return np.where(np.isclose(self.X[:, axis], hi if side else lo))[0]
+
+
+class ExplicitBar:
+    """Central-difference time stepping of the bar under a constant pull velocity.
+
+    provider(F) -> (P, sigma): first Piola-Kirchhoff stress (ngp, 3, 3) and Cauchy stress (ngp, 6)
+    for the deformation gradients F (ngp, 3, 3) of one load step."""
+
+    def __init__(self, mesh, provider, dt, pull_velocity, damping=0.0):
+        self.m, self.provider, self.dt, self.vp, self.c = mesh, provider, dt, pull_velocity, damping
+        self.u = np.zeros((mesh.nnodes, 3))
+        self.v = np.zeros((mesh.nnodes, 3))
+        self.left, self.right = mesh.face(0, 0), mesh.face(0, 1)
+        corner = self.left[np.argmin(mesh.X[self.left, 1] + mesh.X[self.left, 2])]
+        side = self.left[np.argmax(mesh.X[self.left, 1] - mesh.X[self.left, 2])]
+        self.pin_yz, self.pin_z = corner, side
+        self.v[self.right, 0] = pull_velocity
+        self.t = 0.0
+        self.u_pull = 0.0                 # prescribed displacement of the pulled face
+        self.history = []
+
+    def _apply_bc(self):
+        self.v[self.left, 0] = 0.0
+        self.u[self.left, 0] = 0.0
+        self.v[self.right, 0] = self.vp
+        self.u[self.right, 0] = self.u_pull
+        self.v[self.pin_yz, 1:] = 0.0
+        self.u[self.pin_yz, 1:] = 0.0
+        self.v[self.pin_z, 2] = 0.0
+        self.u[self.pin_z, 2] = 0.0
+
+    def step(self):
+        """One load step: stresses at the current configuration, then v and u advance by dt."""
+        F = self.m.deformation_gradients(self.u)
+        P, sigma = self.provider(F)
+        f = -self.m.internal_forces(P)
+        a = f / self.m.mass[:, None] - self.c * self.v
+        self.v += self.dt * a
+        self.t += self.dt
+        self.u_pull += self.dt * self.vp
+        self.u += self.dt * self.v
+        self._apply_bc()
+        strain = self.u_pull / self.m.size[0]
+        self.history.append(dict(strain=strain, F=F, P=P, sigma=sigma,
+                                 tensile=tensile_stress(sigma)))
+        return F, P, sigma
+
+
+def tensile_stress(sigma):
+    """Largest eigenvalue of sigma_FEM averaged over the Gauss points (the measure of Fig. 6)."""
+    s = np.asarray(sigma)
+    m = np.array([[s[:, 0], s[:, 3], s[:, 4]], [s[:, 3], s[:, 1], s[:, 5]], [s[:, 4], s[:, 5], s[:, 2]]])
+    return float(np.linalg.eigvalsh(m.transpose(2, 0, 1))[:, -1].mean())
+
+
+def neo_hookean(mu, lam):
+    """Compressible neo-Hookean material (for checks of the driver): P = mu (F - F^-T) + lam ln J F^-T."""
+    def provider(F):
+        J = np.linalg.det(F)
+        FiT = np.linalg.inv(F).transpose(0, 2, 1)
+        P = mu * (F - FiT) + lam * np.log(J)[:, None, None] * FiT
+        sig = np.einsum("gij,gkj->gik", P, F) / J[:, None, None]
+        return P, np.stack([sig[:, 0, 0], sig[:, 1, 1], sig[:, 2, 2], sig[:, 0, 1], sig[:, 0, 2], sig[:, 1, 2]], 1)
+
+    def energy(F):
+        J = np.linalg.det(F)
+        I1 = np.einsum("gij,gij->g", F, F)
+        return 0.5 * mu * (I1 - 3) - mu * np.log(J) + 0.5 * lam * np.log(J) ** 2
+    provider.energy = energy
+    return provider
+
+
+class MDStress:
+    """Stress provider backed by batched MD r-cells: set_deformation (Eqs. 4, 5, 9), md_steps MD
+    steps, windowed stress rotated back (Eqs. 7, 8).  cells[g] is the r-cell of Gauss point g."""
+
+    def __init__(self, params, cells, md_steps, stream=None):
+        from .rcell import RCellBatch
+        self.g = RCellBatch(params, cells, stream=stream)
+        self.md_steps = md_steps
+        self.last_md = None           # MD-frame stress of the last load step (training targets)
+
+    def __call__(self, F):
+        self.g.set_deformation(F)
+        self.g.run(self.md_steps)
+        s, P, self.last_md = self.g.get_stress_ext()
+        return P, s

@@ -20,10 +20,11 @@ PRECISIONS = {"fp64": 0, "mixed": 1}
 
 # every entry point that include/rcell.h declares
 EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev", "rcell_run",
-           "rcell_get_stress", "rcell_get_stress_dev", "rcell_destroy", "rcell_last_error",
+           "rcell_get_stress", "rcell_get_stress_dev", "rcell_get_stress_ext", "rcell_destroy", "rcell_last_error",
            "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
            "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
-           "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps"]
+           "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps",
+           "rcell_qr_dev", "rcell_stress_return_dev"]
 
 
 class RCellError(RuntimeError):
@@ -64,6 +65,7 @@ def load():
             "rcell_create": [vp, vp, i32, vp, vp], "rcell_set_deformation": [vp, vp],
             "rcell_set_deformation_dev": [vp, vp], "rcell_run": [vp, i32],
             "rcell_get_stress": [vp, vp, vp], "rcell_get_stress_dev": [vp, vp, vp],
+            "rcell_get_stress_ext": [vp, vp, vp, vp],
             "rcell_destroy": [vp], "rcell_last_error": [vp], "rcell_get_status": [vp, vp],
             "rcell_get_forces": [vp, i32, vp], "rcell_get_state": [vp, i32, vp, vp, vp, vp, vp],
             "rcell_set_state": [vp, i32, vp, vp, vp, vp, i64], "rcell_get_energy": [vp, vp, vp],
@@ -71,6 +73,7 @@ def load():
             "rcell_set_lanes": [vp, i32], "rcell_get_lanes": [vp, vp],
             "rcell_prof_enable": [vp, i32], "rcell_prof_read": [vp, i32, vp, vp],
             "rcell_set_graph_steps": [vp, i32],
+            "rcell_qr_dev": [vp, i32, vp, vp, vp, vp], "rcell_stress_return_dev": [vp, vp, i32, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -100,6 +103,20 @@ def _f64(a, shape=None):
 
 def _p(a):
     return None if a is None else a.ctypes.data
+
+
+def qr_dev(F_dev_ptr, n, Q_dev_ptr, R_dev_ptr, status_dev_ptr=None, stream=None):
+    """Eq. (4) for n deformation gradients in device memory (FP64, n x 9)."""
+    st = load().rcell_qr_dev(F_dev_ptr, int(n), Q_dev_ptr, R_dev_ptr, status_dev_ptr, stream)
+    if st != OK:
+        raise RCellError(st, "qr_dev")
+
+
+def stress_return_dev(F_dev_ptr, sigma_md_dev_ptr, n, sigma_fem_dev_ptr, P_dev_ptr=None, stream=None):
+    """Eqs. (7), (8) for n MD-frame stresses in device memory (FP64)."""
+    st = load().rcell_stress_return_dev(F_dev_ptr, sigma_md_dev_ptr, int(n), sigma_fem_dev_ptr, P_dev_ptr, stream)
+    if st != OK:
+        raise RCellError(st, "stress_return_dev")
 
 
 class RCellBatch:
@@ -163,6 +180,12 @@ class RCellBatch:
         P = np.zeros((self.ncells, 3, 3)) if with_P else None
         self._check(load().rcell_get_stress(self._h, _p(s), _p(P)))
         return (s, P) if with_P else s
+
+    def get_stress_ext(self):
+        """(sigma_FEM, P, sigma_MD) of the window, clearing it."""
+        s, P, smd = np.zeros((self.ncells, 6)), np.zeros((self.ncells, 3, 3)), np.zeros((self.ncells, 6))
+        self._check(load().rcell_get_stress_ext(self._h, _p(s), _p(P), _p(smd)))
+        return s, P, smd
 
     def get_stress_dev(self, sigma_dev_ptr, P_dev_ptr=None):
         self._check(load().rcell_get_stress_dev(self._h, sigma_dev_ptr, P_dev_ptr))

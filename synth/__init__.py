@@ -10,9 +10,9 @@ from .fcc import fcc_lattice
 from .kg import kg_melt, kg_box_edge
 from .velocities import maxwell_boltzmann
 from .deform import (random_rotation, uniaxial_isochoric, rotated_uniaxial, rotated_stretch,
-                     TABLE1_F)
+                     stretch_paths, TABLE1_F)
 from . import configs
 
 __all__ = ["splitmix64", "cell_seed", "generator", "fcc_lattice", "kg_melt", "kg_box_edge",
            "maxwell_boltzmann", "random_rotation", "uniaxial_isochoric", "rotated_uniaxial",
-           "rotated_stretch", "TABLE1_F", "configs"]
+           "rotated_stretch", "stretch_paths", "TABLE1_F", "configs"]

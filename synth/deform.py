@@ -43,3 +43,20 @@ def rotated_stretch(rng: np.random.Generator, lo: float = 0.9, hi: float = 1.1) 
     V = random_rotation(rng)
     lam = rng.uniform(lo, hi, 3)
     return Q @ (V @ np.diag(lam) @ V.T)
+
+
+def stretch_paths(ncells, nsteps, rng, rate_max=0.012, nu=(0.2, 0.5), shear=0.01):
+    """Rotation-free deformation paths for surrogate training: per cell, an upper-triangular stretch
+    R_k = U_k with axial stretch lambda_k (increments ~ U[0, rate_max] per load step along x),
+    lateral stretch lambda_k^-nu (nu ~ U[nu]) and small random-walk upper shears.  (ncells, nsteps, 3, 3)."""
+    out = np.zeros((ncells, nsteps, 3, 3))
+    for c in range(ncells):
+        lam, s = 1.0, np.zeros(3)
+        rate = rng.uniform(0.0, rate_max)
+        v = rng.uniform(*nu)
+        for k in range(nsteps):
+            lam *= 1.0 + rate * rng.uniform(0.5, 1.5)
+            s = s + rng.normal(0.0, shear / np.sqrt(nsteps), 3)
+            lt = lam ** (-v)
+            out[c, k] = np.array([[lam, s[0], s[1]], [0.0, lt, s[2]], [0.0, 0.0, lt]])
+    return out

@@ -301,3 +301,27 @@ def test_graph_replay_equals_eager_launches(rc, pot):
         sa, sb = a.get_state(k), b.get_state(k)
         assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["v"], sb["v"])
     assert a.rebuilds() == b.rebuilds()
+
+
+def test_stateless_qr_and_stress_return_match_the_oracle(rc):
+    import torch
+    rng = np.random.default_rng(12)
+    Fs = list(TABLE1_F.values()) + [np.eye(3) + 0.2 * rng.standard_normal((3, 3)) for _ in range(60)]
+    Fs = [F for F in Fs if np.linalg.det(F) > 0.05] + [np.diag([1.0, 1.0, -1.0])]
+    n = len(Fs)
+    F = torch.tensor(np.stack(Fs).reshape(n, 9), dtype=torch.float64, device="cuda:0")
+    Q = torch.zeros_like(F); R = torch.zeros_like(F)
+    st = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    smd = torch.tensor(rng.standard_normal((n, 6)), dtype=torch.float64, device="cuda:0")
+    sf = torch.zeros_like(smd); P = torch.zeros_like(F)
+    rc.qr_dev(F.data_ptr(), n, Q.data_ptr(), R.data_ptr(), st.data_ptr())
+    rc.stress_return_dev(F.data_ptr(), smd.data_ptr(), n, sf.data_ptr(), P.data_ptr())
+    torch.cuda.synchronize()
+    Qh, Rh, sth = Q.cpu().numpy().reshape(n, 3, 3), R.cpu().numpy().reshape(n, 3, 3), st.cpu().numpy()
+    sfh, Ph, smh = sf.cpu().numpy(), P.cpu().numpy().reshape(n, 3, 3), smd.cpu().numpy()
+    for k in range(n - 1):
+        Qo, Ro = core.qr(Fs[k])
+        assert sth[k] == 0 and np.abs(Qh[k] - Qo).max() < 1e-14 and np.abs(Rh[k] - Ro).max() < 1e-14
+        so, Po = core.stress_to_fem(Fs[k], smh[k])
+        assert np.abs(sfh[k] - so).max() < 1e-13 * np.abs(so).max() and np.abs(Ph[k] - Po).max() < 1e-12 * np.abs(Po).max()
+    assert sth[-1] == rc.ERR_BAD_F and np.all(np.isnan(sfh[-1]))
