@@ -61,7 +61,7 @@ typedef struct {
   double lj_eps, lj_sigma; /* KG: LJ truncated at rc and shifted to zero there (WCA at 2^(1/6)) */
   double fene_K, fene_R0;  /* KG: FENE bonds U = -K R0^2/2 ln(1 - (r/R0)^2) */
   double sc_eps, sc_a, sc_c; /* Sutton-Chen: E = sum_i [1/2 sum_j eps phi(r_ij) - eps c sqrt(rho_i)] */
-  int32_t sc_n, sc_m;      /* phi = (a/r)^n - (a/rc)^n, rho_i = sum_j (a/r)^m - (a/rc)^m */
+  int32_t sc_n, sc_m;      /* phi = (a/r)^n - (a/rc)^n, rho_i = sum_j (a/r)^m - (a/rc)^m; 1..31 */
   uint64_t seed;           /* Philox4x32-10 key = (low, high 32 bits of seed) */
   int32_t include_kinetic; /* 1: sigma includes -sum m v (x) v / V (thermal r-cells) */
 } rcell_params;

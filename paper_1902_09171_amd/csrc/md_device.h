@@ -125,15 +125,27 @@ struct Mixed {
     return (int)(unsigned int)(unsigned long long)(long long)rint(f * TWO32);
   }
   __device__ static S make(double f0, double f1, double f2) { return make_int4(fix1(f0), fix1(f1), fix1(f2), 0); }
-  __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) {
+  // the cell's H * 2^-32 (upper triangular: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz) as float hi + lo,
+  // held in registers across a neighbour loop
+  struct Geo { float hi[6], lo[6]; };
+  __device__ static Geo geo(const CellDev& C) {
+    Geo g;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) { g.hi[q] = C.Hhi[q]; g.lo[q] = C.Hlo[q]; }
+    return g;
+  }
+  __device__ static void sep(const S& sj, const S& si, const Geo& g, R d[3]) {
     const float a = (float)(int)((unsigned)sj.x - (unsigned)si.x);
     const float b = (float)(int)((unsigned)sj.y - (unsigned)si.y);
     const float c = (float)(int)((unsigned)sj.z - (unsigned)si.z);
-    // H (upper triangular: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz) applied as hi + lo float pair
-    d[0] = fmaf(C.Hhi[0], a, fmaf(C.Hhi[1], b, C.Hhi[2] * c)) + fmaf(C.Hlo[0], a, fmaf(C.Hlo[1], b, C.Hlo[2] * c));
-    d[1] = fmaf(C.Hhi[3], b, C.Hhi[4] * c) + fmaf(C.Hlo[3], b, C.Hlo[4] * c);
-    d[2] = C.Hhi[5] * c + C.Hlo[5] * c;
+    d[0] = fmaf(g.hi[0], a, fmaf(g.hi[1], b, g.hi[2] * c)) + fmaf(g.lo[0], a, fmaf(g.lo[1], b, g.lo[2] * c));
+    d[1] = fmaf(g.hi[3], b, g.hi[4] * c) + fmaf(g.lo[3], b, g.lo[4] * c);
+    d[2] = g.hi[5] * c + g.lo[5] * c;
   }
+  __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) { sep(sj, si, geo(C), d); }
+  // single hardware instructions (about 1 ulp): ample for FP32 pair forces
+  __device__ static R rsq(R x) { return __builtin_amdgcn_rsqf(x); }
+  __device__ static R rcp(R x) { return __builtin_amdgcn_rcpf(x); }
 };
 
 struct FP64 {
@@ -156,14 +168,24 @@ struct FP64 {
   __device__ static double cvt(long long v) {       // signed 64-bit integer to double, rounded
     return (double)v;
   }
-  __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) {
+  struct Geo { double h[6]; };                     // H * 2^-64, upper triangle
+  __device__ static Geo geo(const CellDev& C) {
+    Geo g;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) g.h[q] = C.Hd[q];
+    return g;
+  }
+  __device__ static void sep(const S& sj, const S& si, const Geo& g, R d[3]) {
     const double a = cvt((long long)((unsigned long long)sj.x - (unsigned long long)si.x));
     const double b = cvt((long long)((unsigned long long)sj.y - (unsigned long long)si.y));
     const double c = cvt((long long)((unsigned long long)sj.z - (unsigned long long)si.z));
-    d[0] = C.Hd[0] * a + C.Hd[1] * b + C.Hd[2] * c;
-    d[1] = C.Hd[3] * b + C.Hd[4] * c;
-    d[2] = C.Hd[5] * c;
+    d[0] = g.h[0] * a + g.h[1] * b + g.h[2] * c;
+    d[1] = g.h[3] * b + g.h[4] * c;
+    d[2] = g.h[5] * c;
   }
+  __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) { sep(sj, si, geo(C), d); }
+  __device__ static R rsq(R x) { return 1.0 / sqrt(x); }
+  __device__ static R rcp(R x) { return 1.0 / x; }
 };
 
 // S = H^-1 x for upper-triangular H^-1, reduced to its fractional part
@@ -183,15 +205,41 @@ __device__ __forceinline__ typename P::S fixed_pos(const CellDev& C, double x, d
   return P::make(f[0], f[1], f[2]);
 }
 
+// t^N for a compile-time exponent (binary powering)
+template <int N, class T>
+__device__ __forceinline__ T powc(T t) {
+  if constexpr (N == 0) return (T)1;
+  else if constexpr (N == 1) return t;
+  else if constexpr (N % 2 == 0) { const T h = powc<N / 2>(t); return h * h; }
+  else return powc<N - 1>(t) * t;
+}
+
+// t^n for a run-time exponent 0 <= n < 32, branch free (the exponent is uniform over the grid)
 template <class T>
-__device__ __forceinline__ T ipow(T t, int n) {
+__device__ __forceinline__ T powr(T t, int n) {
   T r = (T)1;
-  while (n) {
-    if (n & 1) r *= t;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    r = ((n >> b) & 1) ? r * t : r;
     t *= t;
-    n >>= 1;
   }
   return r;
+}
+
+// Sutton-Chen powers tn = t^n and tm = t^m; SN = SM = 0 takes the exponents at run time
+template <int SN, int SM, class T>
+__device__ __forceinline__ void sc_powers(T t, int n, int m, T& tn, T& tm) {
+  if constexpr (SN == 9 && SM == 6) {
+    const T t3 = t * t * t;
+    tm = t3 * t3;
+    tn = tm * t3;
+  } else if constexpr (SN > 0) {
+    tn = powc<SN>(t);
+    tm = powc<SM>(t);
+  } else {
+    tn = powr(t, n);
+    tm = powr(t, m);
+  }
 }
 
 // ------------------------------------------------------------------ block reductions
@@ -419,6 +467,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     const typename P::S si = P::load(a.s_cur, i);
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sig2 = (R)a.lj_sig2, e24 = (R)(24.0 * a.lj_eps), e4 = (R)(4.0 * a.lj_eps), sh = (R)a.lj_shift;
+    const typename P::Geo g = P::geo(C);
     // neighbours k = lane, lane + TPA, ... in that order; UNR index loads and UNR gathers are
     // issued before any arithmetic so that their latencies overlap
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
@@ -436,10 +485,10 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
       for (int u = 0; u < UNR; ++u) {
       if (jj[u] < 0) continue;
       R d[3];
-      P::sep(sj[u], si, C, d);
+      P::sep(sj[u], si, g, d);
       const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       if (r2 < rc2) {
-        const R r2i = (R)1 / r2;
+        const R r2i = P::rcp(r2);
         const R s2 = sig2 * r2i;
         const R s6 = s2 * s2 * s2;
         const R gr = -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i;   // (dU/dr) / r
@@ -459,7 +508,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
       for (int q = 0; q < 4; ++q) {
         if (bp[q] < 0) continue;
         R d[3];
-        P::sep(P::load(a.s_cur, bp[q] + C.off), si, C, d);
+        P::sep(P::load(a.s_cur, bp[q] + C.off), si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         const R tt = r2 / R02;
         if (!(tt < (R)1)) { status = ST_BOND; continue; }
@@ -496,7 +545,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
 }
 
 // Sutton-Chen pass 1: host density rho_i and F'(rho_i) = -eps c / (2 sqrt(rho_i)), stored in s.w
-template <class P, int TPA>
+template <class P, int TPA, int SN, int SM>
 __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   using R = typename P::R;
   const Tile t = a.tiles[blockIdx.x];
@@ -509,6 +558,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
     const typename P::S si = P::load(a.s_cur, i);
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, rhoc = (R)a.sc_rhoc;
+    const typename P::Geo g = P::geo(C);
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
       int jj[UNR];
       typename P::S sj[UNR];
@@ -524,11 +574,12 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
       for (int u = 0; u < UNR; ++u) {
         if (jj[u] < 0) continue;
         R d[3];
-        P::sep(sj[u], si, C, d);
+        P::sep(sj[u], si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         if (r2 < rc2) {
-          const R tr = sa * ((R)1 / sqrt(r2));
-          rho += ipow(tr, a.sc_m) - rhoc;
+          R tn, tm;
+          sc_powers<SN, SM>(sa * P::rsq(r2), a.sc_n, a.sc_m, tn, tm);
+          rho += tm - rhoc;
         }
       }
     }
@@ -541,7 +592,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
 }
 
 // Sutton-Chen pass 2: pair scalar g = eps phi'(r) + (F'_i + F'_j) rho'(r), then the tail
-template <class P, int TPA>
+template <class P, int TPA, int SN, int SM>
 __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
@@ -559,6 +610,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, en = (R)(a.sc_eps * a.sc_n), m = (R)a.sc_m;
     const R eh = (R)(0.5 * a.sc_eps), phic = (R)a.sc_phic;
+    const typename P::Geo g = P::geo(C);
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
       int jj[UNR];
       typename P::S sj[UNR];
@@ -574,13 +626,12 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
       for (int u = 0; u < UNR; ++u) {
         if (jj[u] < 0) continue;
         R d[3];
-        P::sep(sj[u], si, C, d);
+        P::sep(sj[u], si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         if (r2 < rc2) {
-          const R ri = (R)1 / sqrt(r2);
-          const R tr = sa * ri;
-          const R tm = ipow(tr, a.sc_m);
-          const R tn = ipow(tr, a.sc_n);
+          const R ri = P::rsq(r2);
+          R tn, tm;
+          sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
           const R gr = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
           f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
           const R hg = (R)0.5 * gr;

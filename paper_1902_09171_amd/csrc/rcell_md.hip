@@ -198,19 +198,26 @@ struct ProfScope {
   }
 };
 
+template <class P, int TPA, int SN, int SM>
+void force_eam_t(rcell_ctx* c, const MDArgs& a, int mode) {
+  const dim3 grid(c->ntiles), block(TILE * TPA);
+  {
+    ProfScope ps(c, 1);
+    hipLaunchKernelGGL((k_eam_rho<P, TPA, SN, SM>), grid, block, 0, c->stream, a, mode);
+  }
+  ProfScope ps(c, 0);
+  hipLaunchKernelGGL((k_force_eam<P, TPA, SN, SM>), grid, block, 0, c->stream, a, mode);
+}
+
 template <class P, int TPA>
 void force_t(rcell_ctx* c, const MDArgs& a, int mode) {
-  const dim3 grid(c->ntiles), block(TILE * TPA);
   if (c->p.potential == RCELL_POT_KG) {
     ProfScope ps(c, 0);
-    hipLaunchKernelGGL((k_force_kg<P, TPA>), grid, block, 0, c->stream, a, mode);
+    hipLaunchKernelGGL((k_force_kg<P, TPA>), dim3(c->ntiles), dim3(TILE * TPA), 0, c->stream, a, mode);
+  } else if (a.sc_n == 9 && a.sc_m == 6) {      // copper, nickel: exponents fixed at compile time
+    force_eam_t<P, TPA, 9, 6>(c, a, mode);
   } else {
-    {
-      ProfScope ps(c, 1);
-      hipLaunchKernelGGL((k_eam_rho<P, TPA>), grid, block, 0, c->stream, a, mode);
-    }
-    ProfScope ps(c, 0);
-    hipLaunchKernelGGL((k_force_eam<P, TPA>), grid, block, 0, c->stream, a, mode);
+    force_eam_t<P, TPA, 0, 0>(c, a, mode);
   }
 }
 
@@ -423,8 +430,8 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
     return fail(nullptr, RCELL_ERR_ARG, "dt, mass, mvv2e, rc must be > 0; skin, gamma, temperature, kB >= 0");
   if (p.potential == RCELL_POT_KG && (!(p.lj_sigma > 0) || !(p.fene_R0 > 0)))
     return fail(nullptr, RCELL_ERR_ARG, "KG needs lj_sigma > 0 and fene_R0 > 0");
-  if (p.potential == RCELL_POT_SC_EAM && (!(p.sc_a > 0) || p.sc_n < 1 || p.sc_m < 1))
-    return fail(nullptr, RCELL_ERR_ARG, "Sutton-Chen needs sc_a > 0 and n, m >= 1");
+  if (p.potential == RCELL_POT_SC_EAM && (!(p.sc_a > 0) || p.sc_n < 1 || p.sc_m < 1 || p.sc_n > 31 || p.sc_m > 31))
+    return fail(nullptr, RCELL_ERR_ARG, "Sutton-Chen needs sc_a > 0 and 1 <= n, m <= 31");
   const double rcs = p.rc + p.skin;
 
   rcell_ctx* c = new (std::nothrow) rcell_ctx();

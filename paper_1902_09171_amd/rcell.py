@@ -59,6 +59,10 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1902_09171_amd.build")
+        # torch ships its own HIP runtime under the same soname; loading torch first lets the
+        # library bind to that one, so the process holds a single HIP runtime (two copies cannot
+        # share the device, and whichever initialises second reports no GPU)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         sig = {
