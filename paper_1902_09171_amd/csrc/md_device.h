@@ -43,6 +43,9 @@ struct CellDev {
   int off, n, tile_off, ntile;
   int nb[3], bin_off, bin_cap;
   int rebuild, pending, status, pad;
+  double Hb[6];                   // H at the last neighbour build, upper triangle (0 1 2 4 5 8)
+  float hs2;                      // squared displacement that still keeps the list complete
+  int pad2;
 };
 
 struct Tile { int cell, begin, count, pad; };
@@ -731,7 +734,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   if (st != 0 && C.status == 0) C.status = st;
   if (C.rebuild) C.nrebuild += 1;
   if (mode == RED_START) {
-    C.rebuild = md > (float)a.half_skin2;
+    C.rebuild = md > C.hs2;
     C.xi_mean[0] = (double)x0 / (double)C.n;
     C.xi_mean[1] = (double)x1 / (double)C.n;
     C.xi_mean[2] = (double)x2 / (double)C.n;
@@ -754,7 +757,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   C.wcount += 1;
   C.step += 1;
   if (mode == RED_STEP) {
-    C.rebuild = md > (float)a.half_skin2;
+    C.rebuild = md > C.hs2;
     C.xi_mean[0] = (double)x0 / (double)C.n;
     C.xi_mean[1] = (double)x1 / (double)C.n;
     C.xi_mean[2] = (double)x2 / (double)C.n;
@@ -803,10 +806,15 @@ __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
 constexpr int SCAN_NT = 1024;
 __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
   __shared__ int sh[SCAN_NT];
-  const CellDev& C = a.cells[blockIdx.x];
+  CellDev& C = a.cells[blockIdx.x];
   if (!C.rebuild) return;
   const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
   const int t = threadIdx.x;
+  if (t == 0) {                    // the list about to be built holds every pair within rc + skin
+    const int up[6] = {0, 1, 2, 4, 5, 8};
+    for (int q = 0; q < 6; ++q) C.Hb[q] = C.H[up[q]];
+    C.hs2 = (float)a.half_skin2;
+  }
   int carry = 0;
   for (int base = 0; base < nbins; base += SCAN_NT) {   // coalesced chunks of SCAN_NT bins
     const int b = base + t;
@@ -840,11 +848,15 @@ __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
 
-// one lane per bin slot of every cell (grid over the bin capacity).  Bins of up to SMALL_BIN
-// atoms are insertion-sorted by their lane; larger bins are rank-sorted by the whole wave (entry v
-// goes to position #{entries < v}; indices are distinct) through the scratch array, then copied back.
+// one lane per bin slot of every cell (grid over the bin capacity), one wave per block.  When the
+// wave's 64 bins fit in LDS together they are staged there and every lane rank-sorts its own bin
+// (entry v goes to position #{entries < v}; atom indices are distinct) straight back to memory.
+// Otherwise bins of up to SMALL_BIN atoms are insertion-sorted by their lane and larger bins are
+// rank-sorted by the whole wave, one after another, through the scratch array.
 constexpr int SMALL_BIN = 24;
+constexpr int SORT_LDS = 8192;       // staged entries per wave (32 KB)
 __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) {
+  __shared__ int stage[SORT_LDS];
   const long long g = (long long)blockIdx.x * 64 + threadIdx.x;
   int big = 0;                       // this lane's bin needs the wave
   int *p = nullptr, n = 0;
@@ -855,16 +867,36 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
     if (C.rebuild && b < C.nb[0] * C.nb[1] * C.nb[2]) {
       p = a.binned + C.off + a.bstart[g];
       n = a.bnum[g];
-      big = n > SMALL_BIN;
-      if (!big)
-        for (int u = 1; u < n; ++u) {
-          const int v = p[u];
-          int q = u - 1;
-          while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
-          p[q + 1] = v;
-        }
     }
   }
+  int incl = n;                      // exclusive offsets of the 64 bins in the staging array
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o);
+    if ((int)threadIdx.x >= o) incl += v;
+  }
+  const int total = __shfl(incl, 63);
+  if (total == 0) return;
+  if (total <= SORT_LDS) {
+    int* sb = stage + (incl - n);
+    for (int e = 0; e < n; ++e) sb[e] = p[e];
+    __syncthreads();
+    for (int e = 0; e < n; ++e) {
+      const int v = sb[e];
+      int rank = 0;
+      for (int q = 0; q < n; ++q) rank += sb[q] < v;
+      p[rank] = v;
+    }
+    return;
+  }
+  big = n > SMALL_BIN;
+  if (!big)
+    for (int u = 1; u < n; ++u) {
+      const int v = p[u];
+      int q = u - 1;
+      while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
+      p[q + 1] = v;
+    }
   // large bins, one after another, by all 64 lanes
   unsigned long long mask = __ballot(big);
   while (mask) {
@@ -920,6 +952,7 @@ __global__ __launch_bounds__(TILE * LPA) void k_build_list(MDArgs a) {
   }
   const int nq = cnt[0] * cnt[1] * cnt[2];
   const typename P::R rcs2 = (typename P::R)a.rcs2;
+  const typename P::Geo g = P::geo(C);
   int n = 0, base = 0;
   for (int pass = 0; pass < 2; ++pass) {
     int k = base;
@@ -928,14 +961,23 @@ __global__ __launch_bounds__(TILE * LPA) void k_build_list(MDArgs a) {
       const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
       const int* p = a.binned + C.off + a.bstart[C.bin_off + b];
       const int m = a.bnum[C.bin_off + b];
-      for (int e = 0; e < m; ++e) {
-        const int lj = p[e];
-        if (lj == li) continue;
-        typename P::R d[3];
-        P::sep(P::load(a.s_cur, C.off + lj), si, C, d);
-        if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
-          if (pass == 1 && k < a.maxnb) a.nbr[(long long)k * a.npad + i] = lj;
-          ++k;
+      for (int e0 = 0; e0 < m; e0 += UNR) {     // UNR candidates in flight, kept in bin order
+        int lj[UNR];
+        typename P::S sj[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) lj[u] = e0 + u < m ? p[e0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+          if (lj[u] >= 0) sj[u] = P::load(a.s_cur, C.off + lj[u]);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (lj[u] < 0 || lj[u] == li) continue;
+          typename P::R d[3];
+          P::sep(sj[u], si, g, d);
+          if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
+            if (pass == 1 && k < a.maxnb) a.nbr[(long long)k * a.npad + i] = lj[u];
+            ++k;
+          }
         }
       }
     }
@@ -1071,7 +1113,27 @@ __device__ inline void set_box_fields(CellDev& C, double rcs) {
   }
 }
 
-__global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double rcs) {
+// Whether the neighbour list survives a box change.  With A = H Hb^-1 the affine map since the
+// last build and u the largest atom displacement since then (measured in the current box), a pair
+// left out of the list (|d_build| >= rc + skin) is now at least sigma_min(A) (rc + skin) - 2 u
+// apart, and sigma_min(A) >= 1 - |A - I|_F.  The list therefore still holds every pair within rc
+// while u <= ((1 - |A - I|_F)(rc + skin) - rc) / 2; that bound becomes the cell's displacement
+// threshold, and a rebuild is forced only when it is not positive.
+__device__ inline float kept_list_threshold(const CellDev& C, double rc, double rcs) {
+  const double Hb[9] = {C.Hb[0], C.Hb[1], C.Hb[2], 0.0, C.Hb[3], C.Hb[4], 0.0, 0.0, C.Hb[5]};
+  double Hbi[9], A[9];
+  upper_inv(Hb, Hbi);
+  mat3mul(C.H, Hbi, A);
+  double e2 = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    const double d = A[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+    e2 += d * d;
+  }
+  const double hs = 0.5 * ((1.0 - sqrt(e2)) * rcs - rc);
+  return hs > 0.0 ? (float)(hs * hs) : -1.0f;
+}
+
+__global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double rc, double rcs, int force_build) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   CellDev& C = cells[c];
@@ -1083,20 +1145,28 @@ __global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double 
   set_box_fields(C, rcs);
   for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
   C.wcount = 0;
-  C.rebuild = 1;
+  const float hs2 = kept_list_threshold(C, rc, rcs);
+  if (force_build || C.rebuild || !(hs2 > 0.0f)) {
+    C.rebuild = 1;
+  } else {
+    C.hs2 = hs2;
+  }
   C.pending = 1;
 }
 
-// x <- Delta R x for every atom (affine remap, Eq. 6 applied incrementally)
+// x <- Delta R x for every atom (affine remap, Eq. 6 applied incrementally), with the fixed-point
+// scaled coordinates of the remapped positions in the committed box (they equal the old ones up
+// to rounding: the remap leaves S = H^-1 x unchanged)
+template <class P>
 __global__ __launch_bounds__(TILE) void k_remap(MDArgs a, const Stage* st) {
   const Tile t = a.tiles[blockIdx.x];
   if ((int)threadIdx.x >= t.count) return;
   const double* d = st[t.cell].dR;
   const long long i = (long long)t.begin + threadIdx.x;
   const double x = a.x[i], y = a.y[i], z = a.z[i];
-  a.x[i] = d[0] * x + d[1] * y + d[2] * z;
-  a.y[i] = d[4] * y + d[5] * z;
-  a.z[i] = d[8] * z;
+  const double xn = d[0] * x + d[1] * y + d[2] * z, yn = d[4] * y + d[5] * z, zn = d[8] * z;
+  a.x[i] = xn; a.y[i] = yn; a.z[i] = zn;
+  P::store_xyz(a.s_cur, i, fixed_pos<P>(a.cells[t.cell], xn, yn, zn));
 }
 
 // set a cell's box from H (create / set_state) and request a rebuild + prime

@@ -403,10 +403,14 @@ int deformation_common(rcell_ctx* c, const double* F_dev) {
   }
   int e;
   if (grow && (e = layout_bins(c, need))) return e;
-  if ((e = ensure_list_capacity(c, list_capacity(dens, rcs)))) return e;
-  hipLaunchKernelGGL(k_qr_commit, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, c->stage, nc, rcs);
+  const int cap = list_capacity(dens, rcs);
+  const int relist = cap > c->maxnb;               // a reallocated list must be rebuilt everywhere
+  if ((e = ensure_list_capacity(c, cap))) return e;
+  hipLaunchKernelGGL(k_qr_commit, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, c->stage, nc, c->p.rc,
+                     rcs, relist);
   const MDArgs a = make_args(c);
-  hipLaunchKernelGGL(k_remap, dim3(c->ntiles), dim3(TILE), 0, c->stream, a, c->stage);
+  if (c->fp64) hipLaunchKernelGGL(k_remap<FP64>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a, c->stage);
+  else hipLaunchKernelGGL(k_remap<Mixed>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a, c->stage);
   return prime(c);
 }
 

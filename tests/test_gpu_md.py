@@ -281,6 +281,30 @@ def test_neighbour_rebuilds_keep_parity(rc):
     check_forces(g.get_forces(0), fo, TOL["mixed"], "after rebuilds")
 
 
+def test_small_deformations_keep_the_list_exact(rc):
+    # load steps of 0.4 % strain leave the neighbour list in place while the skin still covers the
+    # affine change plus the thermal displacement; the forces after every load step and after the
+    # MD between them must still equal an exact pair enumeration of the same state
+    cfg = configs.cu_element()
+    cells = cfg["cells"][:2]
+    p = cfg["params"]
+    g = rc.RCellBatch(p, cells)
+    g.run(20)
+    n0 = g.rebuilds()
+    F = np.eye(3)
+    nload = 6
+    for k in range(nload):
+        F = F @ np.diag([1.004, 0.998, 0.998])
+        g.set_deformation(np.stack([F, F]))
+        for c in range(2):
+            s = g.get_state(c)
+            fo = core.forces(p, s["H"], s["x"], cells[c]["bonds"])[0]
+            check_forces(g.get_forces(c), fo, TOL["mixed"], f"load step {k} cell {c}")
+        g.run(10)
+    print("rebuilds over", nload, "load steps of 2 cells:", g.rebuilds() - n0, flush=True)
+    assert g.rebuilds() - n0 < 2 * nload
+
+
 @pytest.mark.parametrize("pot", ["kg", "cu"])
 def test_graph_replay_equals_eager_launches(rc, pot):
     # replays of the captured MD-step graphs (with neighbour rebuilds inside) give bit-identical
