@@ -1,13 +1,32 @@
-"""Throughput of batched r-cell MD on one MI355X.
+"""Throughput of batched r-cell MD (and of the learned stress surrogate) on one MI355X.
 
-A step is one finite-element load step of the copper-element workload: for all 8 r-cells
-(4000-atom FCC copper, Sutton-Chen EAM, 300 K Langevin, dt = 1 fs, mixed precision) the device
-resident deformation gradient is QR-decomposed and the boxes remapped, 100 MD steps run
-(neighbour builds, two-pass EAM forces fused with the Langevin velocity-Verlet update, per-cell
-stress reduction), and the window-averaged stress is rotated to the FE frame into device memory.
-Inputs are resident in HBM before the timed region.  Prints one JSON line.
+Workloads (``--workload``; every run prints one JSON line):
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+  cu_element  (default) one hex8 element of copper: 8 FCC r-cells x 4000 atoms, Sutton-Chen EAM,
+              300 K Langevin, dt = 1 fs, mixed precision.  A step is one finite-element load step:
+              the device-resident F of every cell is QR-decomposed and the boxes remapped, 100 MD
+              steps run (neighbour builds, two-pass EAM forces fused with the Langevin
+              velocity-Verlet update, per-cell stress reduction), and the window-averaged stress is
+              rotated to the FE frame into device memory.
+  kg_single   one Kremer-Grest cell of 20 x 50 beads in FP64; F ramped to a 20 % uniaxial
+              isochoric stretch over 1000 MD steps (a new F before every step), stress read every
+              100 steps.  A step is one MD step; latency bound.
+  kg_batched  512 Kremer-Grest cells of 2k-20k beads (chains of 50-200), each under its own
+              rotation x symmetric stretch; mixed precision; a step is 100 MD steps of the whole
+              batch followed by the stress read.
+  fe_bar      the explicit hex8 bar (8 x 2 x 2 elements, 2 x 2 x 2 Gauss points = 256 r-cells of
+              400 x 100 beads, ~10.2 M beads) under uniaxial tension; a step is one FE load step
+              (host FE update, F to the cells, 500 MD steps, stress back).
+  surrogate   the stress surrogate network (153 -> 4 x 256 -> 6, ensemble of 5, BF16 matrix cores
+              with FP32 accumulation): ensemble evaluations per second at the bar's batch (256
+              Gauss points) and at a large batch, and training samples per second.
+
+Inputs are resident in HBM before the timed region; timings bracket K steps with device
+synchronisation.  The roofline object describes the dominant kernel, timed with HIP events on
+the library's own stream.  The CPU baseline is the FP64 oracle on a bounded sample of the same
+workload, on this host's cores.
+
+  python bench.py [--workload W] [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
 import hashlib
@@ -19,15 +38,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MD_PER_LOAD = 100
-PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s
-# algorithmic FLOPs per unique pair inside the cutoff (FMA = 2, other ops 1): Sutton-Chen force
+PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s (published)
+PEAK_HBM = 8.0e12             # MI355X HBM3E, bytes/s (published)
+PEAK_BF16 = 2.5e15            # MI355X dense BF16 matrix, FLOP/s (published)
+# Sutton-Chen: algorithmic FLOPs per unique pair inside the cutoff (FMA = 2, other ops 1): force
 # pass (separation 3, r^2 5, 1/r 2, a/r 1, t^6 3, t^9 2, pair scalar 7, forces on both atoms 12,
 # virial 15, pair energy 3) and density pass (separation 3, r^2 5, 1/r 2, a/r 1, t^6 3, shift 1,
 # both densities 2)
 FLOP_FORCE_PER_PAIR = 53
 FLOP_DENSITY_PER_PAIR = 17
 PAIRS_PER_ATOM = 67           # unique neighbours within 1.95 a in FCC copper
+# Kremer-Grest: the least HBM traffic an MD step needs per bead: x and v in FP64, read and
+# written (96 B), plus the two chain partners as 32-bit indices (8 B)
+BYTES_PER_BEAD_STEP = 104
+
+DEFAULTS = {"cu_element": (50, 3), "kg_single": (1000, 100), "kg_batched": (10, 1), "fe_bar": (4, 1),
+            "surrogate": (200, 20)}
 
 
 def kernel_source_hash():
@@ -38,9 +64,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel):
+def traffic_from_profiles(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 PMC summary, if it matches the source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_cu_element.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -50,51 +76,80 @@ def traffic_from_profiles(kernel):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, sample_steps):
-    """The FP64 oracle on the host cores, on the first load step of the same workload."""
+def fro(s):
+    import numpy as np
+    s = np.asarray(s)
+    return np.sqrt((s[..., :3] ** 2).sum(-1) + 2 * (s[..., 3:] ** 2).sum(-1))
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ MD helpers
+def oracle_sample(params, cells, F, nsteps, label):
+    """The FP64 oracle on the host cores: nsteps MD steps of the given cells after set_deformation(F).
+    Returns (cpu_baseline dict, oracle stress)."""
     from oracle import core
-    ncells = len(cfg["cells"])
-    threads = core.threads(min(ncells, os.cpu_count() or 1))
-    ob = core.OracleBatch(cfg["params"], cfg["cells"])
-    ob.set_deformation(cfg["F_path"][0])
+    threads = core.threads(min(len(cells), os.cpu_count() or 1))
+    ob = core.OracleBatch(params, cells)
+    ob.set_deformation(F)
     ob.get_stress()
     t0 = time.perf_counter()
-    ob.run(sample_steps)
+    ob.run(nsteps)
     dt = time.perf_counter() - t0
-    natoms = sum(len(c["x"]) for c in cfg["cells"])
-    return dict(value=natoms * sample_steps / dt, unit="atom-steps/s", cores=threads, kind="oracle",
-                sample=f"{ncells} cells x {natoms // ncells} atoms x {sample_steps} MD steps of the first load step"), ob.get_stress()
+    natoms = sum(len(c["x"]) for c in cells)
+    return dict(value=natoms * nsteps / dt, unit="atom-steps/s", cores=threads, kind="oracle",
+                sample=f"{len(cells)} cells, {natoms} atoms, {nsteps} MD steps ({label})"), ob.get_stress()
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=25)
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0 = autotune)")
-    ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="first run one plain device copy of this many MiB (calibrates HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the r-cell library runs on one GPU; sharding the cells "
-                                   "over several GPUs is not implemented", "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def gpu_sample_error(rcell, params, cells, F, nsteps, s_ora, lanes):
+    """The same sample on the GPU from the same initial state: max relative stress deviation."""
     import numpy as np
-    import torch
-    from paper_1902_09171_amd import rcell
-    from synth import configs
+    g = rcell.RCellBatch(params, cells)
+    g.set_lanes(lanes)
+    g.set_deformation(F)
+    g.get_stress()
+    g.run(nsteps)
+    s_gpu = g.get_stress()
+    g.close()
+    return float((np.abs(s_gpu - s_ora).max(1) / fro(s_ora)).max())
 
-    if args.copy_probe_mb > 0:
-        n = args.copy_probe_mb * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
+def kernel_avg(g, slot, run_again):
+    """Average HIP-event duration (s) of the force kernel (slot 0) or density pass (slot 1)
+    over a separate pass of run_again(), so that the events do not perturb the timed region."""
+    g.prof_enable(True)
+    g.prof_read(0); g.prof_read(1)
+    run_again()
+    ms, n = g.prof_read(slot)
+    ms1, n1 = g.prof_read(1 - slot)
+    g.prof_enable(False)
+    return (ms / 1e3 / max(n, 1), n), (ms1 / 1e3 / max(n1, 1), n1)
+
+
+def md_line(args, workload, value, elapsed, natoms, config, roofline, extra=None, dtype=None):
+    out = {"metric": "atom-steps/s batched r-cell MD", "value": value, "unit": "atom-steps/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype or "f32 pair forces, f64 positions/integration/stress",
+           "data": "synthetic", "config": dict(workload=workload, **config), "roofline": roofline}
+    if extra:
+        out.update(extra)
+    return out
+
+
+def check_status(g):
+    import numpy as np
+    st = g.status()
+    if np.any(st != 0):
+        raise SystemExit(f"cell status errors during the bench: {st.tolist()}")
+
+
+# ------------------------------------------------------------------ workloads
+def bench_cu_element(args, torch, rcell, configs):
+    import numpy as np
+    MD_PER_LOAD = 100
     cfg = configs.cu_element()
     ncells = len(cfg["cells"])
     natoms = sum(len(c["x"]) for c in cfg["cells"])
@@ -105,7 +160,6 @@ def main():
     F_dev = torch.tensor(np.ascontiguousarray(cfg["F_path"]), dtype=torch.float64, device=dev)
     sig_dev = torch.zeros((ncells, 6), dtype=torch.float64, device=dev)
     P_dev = torch.zeros((ncells, 9), dtype=torch.float64, device=dev)
-
     g.set_deformation_dev(F_dev[0].data_ptr())
     lanes = g.set_lanes(args.lanes)
 
@@ -121,58 +175,324 @@ def main():
     for k in range(args.steps):
         load_step(args.warmup + k)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # kernel durations: the same load steps again, each force-pass launch bracketed by HIP events
-    # on the library's stream (a separate pass, so the events do not perturb the throughput)
+    elapsed = time.perf_counter() - t0
     nprof = min(args.steps, 10)
-    g.prof_enable(True)
-    g.prof_read(0); g.prof_read(1)
-    for k in range(nprof):
-        load_step(args.warmup + args.steps + k)
-    force_ms, force_n = g.prof_read(0)
-    rho_ms, rho_n = g.prof_read(1)
-    g.prof_enable(False)
-    st = g.status()
-    if np.any(st != 0):
-        raise SystemExit(f"cell status errors during the bench: {st.tolist()}")
-    elapsed = t1 - t0
-    atom_steps = natoms * MD_PER_LOAD * args.steps
-    value = atom_steps / elapsed
-
-    # roofline of the dominant kernel (the EAM force pass with the fused integrator)
-    avg_s = force_ms / 1e3 / max(force_n, 1)
+    (avg_s, force_n), (rho_s, _) = kernel_avg(
+        g, 0, lambda: [load_step(args.warmup + args.steps + k) for k in range(nprof)])
+    check_status(g)
+    value = natoms * MD_PER_LOAD * args.steps / elapsed
     flop_launch = FLOP_FORCE_PER_PAIR * PAIRS_PER_ATOM * natoms
     achieved = flop_launch / avg_s
-    traffic = traffic_from_profiles("k_force_eam")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": "k_force_eam",
-                "avg_us": avg_s * 1e6, "launches": force_n,
-                "density_pass_avg_us": rho_ms / 1e3 / max(rho_n, 1) * 1e6,
-                "flop_per_launch": flop_launch}
+                "frac": achieved / PEAK_FP32, "traffic": traffic_from_profiles("k_force_eam", "cu_element"),
+                "kernel": "k_force_eam", "avg_us": avg_s * 1e6, "launches": force_n,
+                "density_pass_avg_us": rho_s * 1e6, "flop_per_launch": flop_launch}
+    out = md_line(args, "cu_element", value, elapsed, natoms,
+                  {"description": "8 FCC copper r-cells x 4000 atoms (one hex8 element, 2x2x2 Gauss "
+                                  "points), Sutton-Chen EAM, 300 K, dt 1 fs, rotated uniaxial F ramp to 5 %, "
+                                  "100 MD steps per load step",
+                   "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
+                   "lanes_per_atom": lanes}, roofline)
+    if not args.no_cpu_baseline:
+        cb, s_ora = oracle_sample(cfg["params"], cfg["cells"], cfg["F_path"][0], args.cpu_sample_steps,
+                                  "first load step of the same element")
+        out["cpu_baseline"] = cb
+        out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cfg["cells"], cfg["F_path"][0],
+                                                           args.cpu_sample_steps, s_ora, lanes)
+    return out
 
-    out = {"metric": "atom-steps/s batched r-cell MD", "value": value, "unit": "atom-steps/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32 pair forces, f64 positions/integration/stress",
-           "data": "synthetic",
-           "config": {"workload": "cu_element: 8 FCC copper r-cells x 4000 atoms (one hex8 element, "
-                                  "2x2x2 Gauss points), Sutton-Chen EAM, 300 K, dt 1 fs, rotated "
-                                  "uniaxial F ramp to 5 %, 100 MD steps per load step",
-                      "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
-                      "lanes_per_atom": lanes},
+
+def bench_kg_single(args, torch, rcell, configs):
+    import numpy as np
+    cfg = configs.kg_single()
+    natoms = len(cfg["cells"][0]["x"])
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    g = rcell.RCellBatch(cfg["params"], cfg["cells"], stream=stream.cuda_stream)
+    F_dev = torch.tensor(np.ascontiguousarray(cfg["F_path"]), dtype=torch.float64, device=dev)
+    sig_dev = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+    nF = len(cfg["F_path"])
+    lanes = g.set_lanes(args.lanes)
+
+    def md_step(k):                                   # F of step k, one MD step, stress every 100
+        g.set_deformation_dev(F_dev[k % nF].data_ptr())
+        g.run(1)
+        if (k + 1) % 100 == 0:
+            g.get_stress_dev(sig_dev.data_ptr(), None)
+
+    for k in range(args.warmup):
+        md_step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        md_step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # plain MD of the same cell (no deformation between steps), graph-captured blocks
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.run(1000)
+    torch.cuda.synchronize()
+    plain_us = (time.perf_counter() - t1) / 1000 * 1e6
+    (avg_s, n), _ = kernel_avg(g, 0, lambda: g.run(100))
+    check_status(g)
+    achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": None, "kernel": "k_force_kg", "avg_us": avg_s * 1e6,
+                "launches": n, "note": "1000 beads cannot fill 256 CUs: latency bound"}
+    out = md_line(args, "kg_single", natoms * args.steps / elapsed, elapsed, natoms,
+                  {"description": "one Kremer-Grest cell, 20 chains x 50 beads, FP64, F ramped to a 20 % "
+                                  "uniaxial isochoric stretch over 1000 MD steps (new F before every step), "
+                                  "stress every 100 steps", "cells": 1, "atoms": natoms,
+                   "md_steps_per_step": 1, "lanes_per_atom": lanes}, roofline,
+                  extra={"us_per_md_step_with_new_F": elapsed / args.steps * 1e6,
+                         "us_per_md_step_plain_run": plain_us}, dtype="f64")
+    if not args.no_cpu_baseline:
+        cb, s_ora = oracle_sample(cfg["params"], cfg["cells"], cfg["F_path"][0], 1000,
+                                  "1000 MD steps of the same cell at the first F")
+        out["cpu_baseline"] = cb
+        out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cfg["cells"], cfg["F_path"][0],
+                                                           1000, s_ora, lanes)
+    return out
+
+
+def make_cells(fn, arg_list):
+    """Generate the KG melts in this process (host-side input preparation, untimed; the melt
+    relaxation is itself multithreaded), with a progress line every 32 cells."""
+    out = []
+    for k, a in enumerate(arg_list):
+        out.append(fn(a))
+        if (k + 1) % 32 == 0 or k + 1 == len(arg_list):
+            log(f"  {k + 1}/{len(arg_list)} cells")
+    return out
+
+
+def _kg_batched_cell(c):
+    from synth import configs
+    out = configs.kg_batched(cells_subset=[c])
+    return out["cells"][0], out["F"][0]
+
+
+def _fe_bar_cell(c):
+    from synth import configs
+    return configs.fe_bar_cells(cells_subset=[c])["cells"][0]
+
+
+def bench_kg_batched(args, torch, rcell, configs):
+    import numpy as np
+    MD_PER_STEP = 100
+    ncells = 512
+    log(f"generating {ncells} Kremer-Grest cells")
+    res = make_cells(_kg_batched_cell, list(range(ncells)))
+    cells = [r[0] for r in res]
+    F = np.stack([r[1] for r in res])
+    params = configs.kg_params(precision="mixed")
+    natoms = sum(len(c["x"]) for c in cells)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    log(f"creating the batch: {natoms} beads")
+    g = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)
+    g.set_deformation(F)
+    lanes = g.set_lanes(args.lanes)
+    sig_dev = torch.zeros((ncells, 6), dtype=torch.float64, device=dev)
+
+    def step():
+        g.run(MD_PER_STEP)
+        g.get_stress_dev(sig_dev.data_ptr(), None)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        if k % 5 == 4:
+            torch.cuda.synchronize()
+            log(f"step {k + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    (avg_s, n), _ = kernel_avg(g, 0, lambda: g.run(100))
+    check_status(g)
+    achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": traffic_from_profiles("k_force_kg", "kg_batched"),
+                "kernel": "k_force_kg", "avg_us": avg_s * 1e6, "launches": n,
+                "bytes_per_launch": BYTES_PER_BEAD_STEP * natoms}
+    out = md_line(args, "kg_batched", natoms * MD_PER_STEP * args.steps / elapsed, elapsed, natoms,
+                  {"description": "512 Kremer-Grest cells of 2k-20k beads (chains 50-200, density 0.85), "
+                                  "each under its own rotation x symmetric stretch (eigenvalues 0.9-1.1), "
+                                  "Langevin T = 1, dt 0.005; 100 MD steps per step",
+                   "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_STEP,
+                   "lanes_per_atom": lanes, "rebuilds": g.rebuilds()}, roofline)
+    if not args.no_cpu_baseline:
+        sub = list(range(16))
+        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F[sub], 20, "the first 16 cells, 20 MD steps")
+        out["cpu_baseline"] = cb
+        out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F[sub], 20,
+                                                           s_ora, lanes)
+    return out
+
+
+def bench_fe_bar(args, torch, rcell, configs):
+    import numpy as np
+    from paper_1902_09171_amd import fe
+    MD_PER_LOAD = 500
+    mesh = fe.Hex8Bar(nel=(8, 2, 2), size=(200.0, 50.0, 50.0), rho0=0.85, imperfection=0.95)
+    log(f"generating {mesh.ngp} r-cells of 40000 beads")
+    cells = make_cells(_fe_bar_cell, list(range(mesh.ngp)))
+    params = configs.kg_params(precision="mixed")
+    natoms = sum(len(c["x"]) for c in cells)
+    log(f"creating the batch: {natoms} beads")
+    md = fe.MDStress(params, cells, MD_PER_LOAD)
+    lanes = md.g.set_lanes(args.lanes)
+    dt = MD_PER_LOAD * params["dt"]
+    # 100 % nominal strain over 100 load steps
+    bar = fe.ExplicitBar(mesh, md, dt=dt, pull_velocity=0.01 * mesh.size[0] / dt, damping=0.2)
+    for _ in range(args.warmup):
+        bar.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        bar.step()
+        log(f"load step {k + 1}/{args.steps}: tensile stress {bar.history[-1]['tensile']:.4f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    (avg_s, n), _ = kernel_avg(md.g, 0, lambda: md.g.run(100))
+    check_status(md.g)
+    achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": traffic_from_profiles("k_force_kg", "fe_bar"),
+                "kernel": "k_force_kg", "avg_us": avg_s * 1e6, "launches": n,
+                "bytes_per_launch": BYTES_PER_BEAD_STEP * natoms}
+    out = md_line(args, "fe_bar", natoms * MD_PER_LOAD * args.steps / elapsed, elapsed, natoms,
+                  {"description": "explicit hex8 bar 8x2x2 elements x 8 Gauss points = 256 Kremer-Grest "
+                                  "r-cells of 400 chains x 100 beads, imperfection-seeded neck, 1 % nominal "
+                                  "strain per load step, 500 MD steps per load step",
+                   "cells": mesh.ngp, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
+                   "lanes_per_atom": lanes, "rebuilds": md.g.rebuilds()}, roofline,
+                  extra={"fe_wall_s_per_load_step": elapsed / args.steps})
+    if not args.no_cpu_baseline:
+        sub = list(range(4))
+        F = np.stack([np.eye(3)] * len(sub))
+        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F, 20, "4 of the bar's cells, 20 MD steps")
+        out["cpu_baseline"] = cb
+        out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F, 20,
+                                                           s_ora, lanes)
+    return out
+
+
+def bench_surrogate(args, torch, rcell, configs):
+    import numpy as np
+    from paper_1902_09171_amd import rsur
+    from synth.surrogate import init_params
+    DIN, WIDTH, DEPTH, DOUT, K = 153, 256, 4, 6, 5
+    B_BAR, B_BIG, B_TRAIN = 256, 65536, 4096
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)            # an explicit stream: the events below time it
+    net = rsur.Surrogate(din=DIN, width=WIDTH, depth=DEPTH, dout=DOUT, ensemble=K, max_batch=B_BIG,
+                         stream=stream.cuda_stream)
+    for k in range(K):
+        net.set_params(k, init_params(net.dims, 7, k))
+    macs = DIN * WIDTH + (DEPTH - 1) * WIDTH * WIDTH + WIDTH * DOUT
+    flop_eval = 2 * macs                              # per evaluation per member
+    gen = torch.Generator(device=dev).manual_seed(1)
+    X = torch.randn((B_BIG, DIN), generator=gen, device=dev, dtype=torch.float32)
+    Y = torch.randn((B_BIG, DOUT), generator=gen, device=dev, dtype=torch.float32)
+    mean = torch.zeros((B_BIG, DOUT), device=dev)
+    var = torch.zeros_like(mean)
+    torch.cuda.synchronize()
+    net.fit_norm(X.data_ptr(), Y.data_ptr(), B_BIG)
+
+    def timed(fn, reps):
+        for _ in range(max(1, reps // 10)):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, e0.elapsed_time(e1) / 1e3 / reps
+
+    fwd_bar = lambda: net.forward(X.data_ptr(), B_BAR, mean.data_ptr(), var.data_ptr())
+    fwd_big = lambda: net.forward(X.data_ptr(), B_BIG, mean.data_ptr(), var.data_ptr())
+    trn = lambda: net.train_step(X.data_ptr(), Y.data_ptr(), B_TRAIN, 1e-4, want_loss=False)
+    for _ in range(args.warmup):
+        fwd_bar()
+    t_bar, ev_bar = timed(fwd_bar, args.steps)
+    t_big, ev_big = timed(fwd_big, max(10, args.steps // 10))
+    t_trn, ev_trn = timed(trn, max(10, args.steps // 4))
+    achieved = flop_eval * K * B_BIG / ev_big
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_BF16, "traffic": None,
+                "kernel": "forward pass (k_norm_in, 5 k_gemm layers over the ensemble, k_ensemble)",
+                "avg_us": ev_big * 1e6, "batch": B_BIG, "flop_per_launch": flop_eval * K * B_BIG}
+    out = {"metric": "surrogate stress-evals/s (ensemble of 5)", "value": B_BAR / t_bar, "unit": "evals/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_bar * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 matrix products, f32 accumulation and master weights", "data": "synthetic",
+           "config": {"workload": "surrogate", "description": "MLP 153 -> 4 x 256 -> 6, ensemble of 5, "
+                      "random-init weights; a step is one ensemble evaluation of the FE bar's 256 Gauss "
+                      "points", "batch": B_BAR, "params_per_member": macs + 4 * WIDTH + DOUT},
+           "evals_per_s_large_batch": B_BIG / t_big, "large_batch": B_BIG,
+           "train_samples_per_s": B_TRAIN / t_trn, "train_batch": B_TRAIN,
            "roofline": roofline}
     if not args.no_cpu_baseline:
-        cb, s_ora = cpu_baseline(cfg, args.cpu_sample_steps)
-        # the same sample on the GPU from the same initial state: stress error of this run
-        g2 = rcell.RCellBatch(cfg["params"], cfg["cells"], stream=stream.cuda_stream)
-        g2.set_lanes(lanes)
-        g2.set_deformation(cfg["F_path"][0])
-        g2.get_stress()
-        g2.run(args.cpu_sample_steps)
-        s_gpu = g2.get_stress()
-        fro = np.sqrt((s_ora[:, :3] ** 2).sum(1) + 2 * (s_ora[:, 3:] ** 2).sum(1))
-        out["cpu_baseline"] = cb
-        out["stress_rel_err_vs_oracle"] = float((np.abs(s_gpu - s_ora).max(1) / fro).max())
+        from oracle import surrogate as osur
+        Ws = [net.get_params(k) for k in range(K)]
+        Xh = X[:B_BAR].double().cpu().numpy()
+        reps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 2.0:
+            for k in range(K):
+                osur.forward(Ws[k], net.dims, Xh)
+            reps += 1
+        dt = (time.perf_counter() - t0) / reps
+        out["cpu_baseline"] = {"value": B_BAR / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+                               "sample": f"FP64 numpy forward of the 5 members on {B_BAR} inputs, {reps} repeats"}
+    return out
+
+
+WORKLOADS = {"cu_element": bench_cu_element, "kg_single": bench_kg_single, "kg_batched": bench_kg_batched,
+             "fe_bar": bench_fe_bar, "surrogate": bench_surrogate}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="cu_element", choices=sorted(WORKLOADS))
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=25)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0 = autotune)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the r-cell library runs on one GPU; sharding the cells "
+                                   "over several GPUs is not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    d_steps, d_warm = DEFAULTS[args.workload]
+    args.steps = d_steps if args.steps is None else args.steps
+    args.warmup = d_warm if args.warmup is None else args.warmup
+
+    import torch
+    from paper_1902_09171_amd import rcell
+    from synth import configs
+    rcell.load()
+
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    out = WORKLOADS[args.workload](args, torch, rcell, configs)
     print(json.dumps(out), flush=True)
 
 

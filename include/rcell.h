@@ -36,7 +36,7 @@ enum {
   RCELL_ERR_BOX = -3,        /* a perpendicular cell width w satisfies w/2 < rc + skin */
   RCELL_ERR_BOND = -4,       /* a FENE bond reached r >= R0 */
   RCELL_ERR_NONFINITE = -5,  /* a returned stress is not finite */
-  RCELL_ERR_OOM = -6,        /* device or host allocation failed */
+  RCELL_ERR_OOM = -6,        /* device or host allocation failed, or a neighbour list beyond 2^32 entries */
   RCELL_ERR_DEVICE = -7,     /* a HIP runtime call failed */
   RCELL_ERR_STATE = -8       /* invalid state (bad box in set_state, neighbour capacity exceeded) */
 };

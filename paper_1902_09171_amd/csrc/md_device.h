@@ -20,6 +20,8 @@
 namespace rcell {
 
 constexpr int TILE = 64;
+constexpr int BIN_BITS = 10;     // bins per dimension < 2^BIN_BITS (bin coordinates are packed)
+constexpr int BIN_MASK = (1 << BIN_BITS) - 1;
 constexpr int UNR = 4;           // neighbour-loop unroll: gathers in flight per lane
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWOM32 = 1.0 / 4294967296.0;
@@ -38,7 +40,7 @@ struct CellDev {
   double wsum[6], last[6];        // stress window sum and last sample (Voigt, tension +)
   double pe;
   double Hd[6];                   // H * 2^-64, upper triangle (FP64 mode)
-  float Hhi[6], Hlo[6];           // H * 2^-32 as float hi + lo (mixed mode)
+  double Hm[6];                   // H * 2^-32, upper triangle (mixed mode)
   long long wcount, step, nrebuild;
   int off, n, tile_off, ntile;
   int nb[3], bin_off, bin_cap;
@@ -120,6 +122,10 @@ struct Mixed {
   using R = float;
   using Fst = double;   // stored total force: touched once per run, kept in FP64 so runs split bitwise
   __device__ static S load(const void* p, long long i) { return ((const int4*)p)[i]; }
+  // element j of a per-cell base pointer, as a 32-bit unsigned byte offset
+  __device__ static S load_rel(const S* base, int j) {
+    return *(const S*)((const char*)base + ((unsigned)j << 4));
+  }
   __device__ static void store_xyz(void* p, long long i, const S& v) { ((int4*)p)[i] = v; }
   __device__ static void store_w(void* p, long long i, R fp) { ((int4*)p)[i].w = __float_as_int(fp); }
   __device__ static R get_w(const S& v) { return __int_as_float(v.w); }
@@ -128,22 +134,24 @@ struct Mixed {
     return (int)(unsigned int)(unsigned long long)(long long)rint(f * TWO32);
   }
   __device__ static S make(double f0, double f1, double f2) { return make_int4(fix1(f0), fix1(f1), fix1(f2), 0); }
-  // the cell's H * 2^-32 (upper triangular: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz) as float hi + lo,
-  // held in registers across a neighbour loop
-  struct Geo { float hi[6], lo[6]; };
+  // the cell's H * 2^-32 (upper triangular: 0 xx, 1 xy, 2 xz, 3 yy, 4 yz, 5 zz), held in
+  // registers across a neighbour loop.  The separation H dS is formed in FP64 (full rate on this
+  // GPU, like FP32 without packing) and rounded once to FP32, so no rounding of H acts as a
+  // strain of the whole cell.
+  struct Geo { double h[6]; };
   __device__ static Geo geo(const CellDev& C) {
     Geo g;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { g.hi[q] = C.Hhi[q]; g.lo[q] = C.Hlo[q]; }
+    for (int q = 0; q < 6; ++q) g.h[q] = C.Hm[q];
     return g;
   }
   __device__ static void sep(const S& sj, const S& si, const Geo& g, R d[3]) {
-    const float a = (float)(int)((unsigned)sj.x - (unsigned)si.x);
-    const float b = (float)(int)((unsigned)sj.y - (unsigned)si.y);
-    const float c = (float)(int)((unsigned)sj.z - (unsigned)si.z);
-    d[0] = fmaf(g.hi[0], a, fmaf(g.hi[1], b, g.hi[2] * c)) + fmaf(g.lo[0], a, fmaf(g.lo[1], b, g.lo[2] * c));
-    d[1] = fmaf(g.hi[3], b, g.hi[4] * c) + fmaf(g.lo[3], b, g.lo[4] * c);
-    d[2] = g.hi[5] * c + g.lo[5] * c;
+    const double a = (double)(int)((unsigned)sj.x - (unsigned)si.x);
+    const double b = (double)(int)((unsigned)sj.y - (unsigned)si.y);
+    const double c = (double)(int)((unsigned)sj.z - (unsigned)si.z);
+    d[0] = (float)fma(g.h[0], a, fma(g.h[1], b, g.h[2] * c));
+    d[1] = (float)fma(g.h[3], b, g.h[4] * c);
+    d[2] = (float)(g.h[5] * c);
   }
   __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) { sep(sj, si, geo(C), d); }
   // single hardware instructions (about 1 ulp): ample for FP32 pair forces
@@ -156,6 +164,9 @@ struct FP64 {
   using R = double;
   using Fst = double;
   __device__ static S load(const void* p, long long i) { return ((const S64*)p)[i]; }
+  __device__ static S load_rel(const S* base, int j) {
+    return *(const S*)((const char*)base + ((unsigned)j << 5));
+  }
   __device__ static void store_xyz(void* p, long long i, const S& v) { ((S64*)p)[i] = v; }
   __device__ static void store_w(void* p, long long i, R fp) { ((S64*)p)[i].w = __double_as_longlong(fp); }
   __device__ static R get_w(const S& v) { return __longlong_as_double(v.w); }
@@ -451,6 +462,25 @@ __device__ __forceinline__ void write_part(Part* parts, const double W[6], const
 }
 
 // ------------------------------------------------------------------ force kernels
+// UNR neighbours of atom i: list slots k0, k0 + TPA, ...  Slots at or past nn re-read the last
+// entry (in bounds) and come back with ok = false, so the pair loops run straight-line code and
+// mask those slots out.  All UNR index loads, then all UNR gathers, are issued before any
+// arithmetic so that their latencies overlap.  sc points at the cell's first atom.
+template <class P, int TPA>
+__device__ __forceinline__ void gather_nbrs(const MDArgs& a, const typename P::S* sc, long long i, int nn, int k0,
+                                            typename P::S sj[UNR], bool ok[UNR]) {
+  int jj[UNR];
+  const unsigned np = (unsigned)a.npad, ii = (unsigned)i;   // the list holds < 2^32 entries
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) {
+    const int k = k0 + u * TPA;
+    ok[u] = k < nn;
+    jj[u] = a.nbr[(unsigned)min(k, nn - 1) * np + ii];
+  }
+#pragma unroll
+  for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, jj[u]);
+}
+
 // Kremer-Grest: LJ truncated and shifted at rc on every listed pair + FENE on bonds; then the
 // integration tail.  TPA lanes share one atom's neighbour list.
 template <class P, int TPA>
@@ -471,36 +501,27 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sig2 = (R)a.lj_sig2, e24 = (R)(24.0 * a.lj_eps), e4 = (R)(4.0 * a.lj_eps), sh = (R)a.lj_shift;
     const typename P::Geo g = P::geo(C);
-    // neighbours k = lane, lane + TPA, ... in that order; UNR index loads and UNR gathers are
-    // issued before any arithmetic so that their latencies overlap
+    const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
+    // neighbours k = lane, lane + TPA, ... in that order
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
-      int jj[UNR];
       typename P::S sj[UNR];
+      bool ok[UNR];
+      gather_nbrs<P, TPA>(a, sc, i, nn, k0, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int k = k0 + u * TPA;
-        jj[u] = k < nn ? a.nbr[(long long)k * a.npad + i] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u)
-        if (jj[u] >= 0) sj[u] = P::load(a.s_cur, jj[u] + C.off);
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-      if (jj[u] < 0) continue;
-      R d[3];
-      P::sep(sj[u], si, g, d);
-      const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      if (r2 < rc2) {
+        R d[3];
+        P::sep(sj[u], si, g, d);
+        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const bool in = ok[u] && r2 < rc2;
         const R r2i = P::rcp(r2);
         const R s2 = sig2 * r2i;
         const R s6 = s2 * s2 * s2;
-        const R gr = -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i;   // (dU/dr) / r
+        const R gr = in ? -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i : (R)0;   // (dU/dr) / r
         f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
         const R hg = (R)0.5 * gr;
         w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
         w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
-        pe += (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh);
-      }
+        pe += in ? (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh) : (R)0;
       }
     }
     if (lane == 0) {
@@ -511,7 +532,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
       for (int q = 0; q < 4; ++q) {
         if (bp[q] < 0) continue;
         R d[3];
-        P::sep(P::load(a.s_cur, bp[q] + C.off), si, g, d);
+        P::sep(P::load_rel(sc, bp[q]), si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         const R tt = r2 / R02;
         if (!(tt < (R)1)) { status = ST_BOND; continue; }
@@ -562,28 +583,19 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, rhoc = (R)a.sc_rhoc;
     const typename P::Geo g = P::geo(C);
+    const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
-      int jj[UNR];
       typename P::S sj[UNR];
+      bool ok[UNR];
+      gather_nbrs<P, TPA>(a, sc, i, nn, k0, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int k = k0 + u * TPA;
-        jj[u] = k < nn ? a.nbr[(long long)k * a.npad + i] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u)
-        if (jj[u] >= 0) sj[u] = P::load(a.s_cur, jj[u] + C.off);
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        if (jj[u] < 0) continue;
         R d[3];
         P::sep(sj[u], si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 < rc2) {
-          R tn, tm;
-          sc_powers<SN, SM>(sa * P::rsq(r2), a.sc_n, a.sc_m, tn, tm);
-          rho += tm - rhoc;
-        }
+        R tn, tm;
+        sc_powers<SN, SM>(sa * P::rsq(r2), a.sc_n, a.sc_m, tn, tm);
+        rho += (ok[u] && r2 < rc2) ? tm - rhoc : (R)0;
       }
     }
   }
@@ -614,34 +626,27 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, en = (R)(a.sc_eps * a.sc_n), m = (R)a.sc_m;
     const R eh = (R)(0.5 * a.sc_eps), phic = (R)a.sc_phic;
     const typename P::Geo g = P::geo(C);
+    const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
-      int jj[UNR];
       typename P::S sj[UNR];
+      bool ok[UNR];
+      gather_nbrs<P, TPA>(a, sc, i, nn, k0, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int k = k0 + u * TPA;
-        jj[u] = k < nn ? a.nbr[(long long)k * a.npad + i] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < UNR; ++u)
-        if (jj[u] >= 0) sj[u] = P::load(a.s_cur, jj[u] + C.off);
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        if (jj[u] < 0) continue;
         R d[3];
         P::sep(sj[u], si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 < rc2) {
-          const R ri = P::rsq(r2);
-          R tn, tm;
-          sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
-          const R gr = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
-          f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-          const R hg = (R)0.5 * gr;
-          w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-          w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
-          pe += eh * (tn - phic);
-        }
+        const bool in = ok[u] && r2 < rc2;
+        const R ri = P::rsq(r2);
+        R tn, tm;
+        sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
+        const R g0 = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
+        const R gr = in ? g0 : (R)0;
+        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+        const R hg = (R)0.5 * gr;
+        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+        pe += in ? eh * (tn - phic) : (R)0;
       }
     }
   }
@@ -799,7 +804,7 @@ __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
 #pragma unroll
   for (int q = 0; q < 3; ++q) b[q] = min((int)(f[q] * C.nb[q]), C.nb[q] - 1);
   const int bin = (b[0] * C.nb[1] + b[1]) * C.nb[2] + b[2];
-  a.abin[i] = bin;
+  a.abin[i] = b[0] | (b[1] << BIN_BITS) | (b[2] << (2 * BIN_BITS));   // packed bin coordinates
   atomicAdd(&a.bcount[C.bin_off + bin], 1);
 }
 
@@ -843,7 +848,8 @@ __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild || (int)threadIdx.x >= t.count) return;
   const long long i = (long long)t.begin + threadIdx.x;
-  const int bin = a.abin[i];
+  const int pk = a.abin[i];
+  const int bin = ((pk & BIN_MASK) * C.nb[1] + ((pk >> BIN_BITS) & BIN_MASK)) * C.nb[2] + (pk >> (2 * BIN_BITS));
   const int slot = atomicAdd(&a.bfill[C.bin_off + bin], 1);
   a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
@@ -921,35 +927,43 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
 }
 
 // Verlet list of every atom: cell-local j with |d| < rc + skin over the 27 (distinct) neighbour
-// bins.  LPA lanes share one atom; lane l scans bins l, l + LPA, ...  Each lane counts its
+// bins.  LPA lanes share one atom and lane l scans bin l, so the dependent loads of a bin (its
+// range, its atom indices, their positions) are the only latency chain.  Each lane counts its
 // neighbours, an exclusive scan over the lanes gives its offset, and a second scan writes them:
-// the list order (lane-major over bins, ascending index inside a bin) is deterministic.
+// the list order (bin by bin, ascending index inside a bin) is deterministic.  A block covers
+// BUILD_ATOMS atoms, so TILE / BUILD_ATOMS blocks cover one tile.
 constexpr int LPA = 8;
+constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
 template <class P>
-__global__ __launch_bounds__(TILE * LPA) void k_build_list(MDArgs a) {
-  const Tile t = a.tiles[blockIdx.x];
+__global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
+  constexpr int PER_TILE = TILE / BUILD_ATOMS;
+  const Tile t = a.tiles[blockIdx.x / PER_TILE];
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild) return;
-  const int slot = threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int slot = (blockIdx.x % PER_TILE) * BUILD_ATOMS + threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const bool active = slot < t.count;
   const long long i = (long long)t.begin + (active ? slot : 0);
   const int li = (int)(i - C.off);
   const typename P::S si = P::load(a.s_cur, i);
-  const int bin = a.abin[i];
-  const int b2 = bin % C.nb[2], b1 = (bin / C.nb[2]) % C.nb[1], b0 = bin / (C.nb[2] * C.nb[1]);
+  const int pk = a.abin[i];
+  const int bb[3] = {pk & BIN_MASK, (pk >> BIN_BITS) & BIN_MASK, pk >> (2 * BIN_BITS)};
+  // neighbour bin coordinates per dimension: b - 1, b, b + 1 (periodic), or every bin when the
+  // dimension has fewer than three
   int lst[3][3], cnt[3];
-  const int bb[3] = {b0, b1, b2};
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int nbq = C.nb[q];
     if (nbq >= 3) {
       cnt[q] = 3;
-      lst[q][0] = (bb[q] + nbq - 1) % nbq; lst[q][1] = bb[q]; lst[q][2] = (bb[q] + 1) % nbq;
+      lst[q][0] = bb[q] == 0 ? nbq - 1 : bb[q] - 1;
+      lst[q][1] = bb[q];
+      lst[q][2] = bb[q] + 1 == nbq ? 0 : bb[q] + 1;
     } else {
       cnt[q] = nbq;
-      for (int u = 0; u < nbq; ++u) lst[q][u] = u;
+      lst[q][0] = 0; lst[q][1] = 1; lst[q][2] = 2;
     }
   }
+  const bool full = cnt[0] == 3 && cnt[1] == 3 && cnt[2] == 3;
   const int nq = cnt[0] * cnt[1] * cnt[2];
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
@@ -957,7 +971,12 @@ __global__ __launch_bounds__(TILE * LPA) void k_build_list(MDArgs a) {
   for (int pass = 0; pass < 2; ++pass) {
     int k = base;
     for (int q = lane; q < nq && active; q += LPA) {
-      const int u0 = q / (cnt[1] * cnt[2]), u1 = (q / cnt[2]) % cnt[1], u2 = q % cnt[2];
+      int u0, u1, u2;
+      if (full) {                               // division by constants
+        u0 = q / 9; u1 = (q / 3) % 3; u2 = q % 3;
+      } else {
+        u0 = q / (cnt[1] * cnt[2]); u1 = (q / cnt[2]) % cnt[1]; u2 = q % cnt[2];
+      }
       const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
       const int* p = a.binned + C.off + a.bstart[C.bin_off + b];
       const int m = a.bnum[C.bin_off + b];
@@ -1084,7 +1103,7 @@ __global__ void k_qr_stage(const double* Fall, const CellDev* cells, Stage* st, 
   box_widths(S.Hn, w);
   S.wmin = fmin(w[0], fmin(w[1], w[2]));
   if (rcs > 0.5 * S.wmin) { S.status = ST_BOX; return; }
-  for (int q = 0; q < 3; ++q) S.nb[q] = max(1, (int)floor(w[q] / rcs));
+  for (int q = 0; q < 3; ++q) S.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / rcs)));
   S.nbins = S.nb[0] * S.nb[1] * S.nb[2];
   S.density = (double)C.n / fabs(det3(S.Hn));
 }
@@ -1096,14 +1115,12 @@ __device__ inline void set_box_fields(CellDev& C, double rcs) {
   const int up[6] = {0, 1, 2, 4, 5, 8};
   for (int q = 0; q < 6; ++q) {
     const double hs = C.H[up[q]] * TWOM32;
-    const float hi = (float)hs;
-    C.Hhi[q] = hi;
-    C.Hlo[q] = (float)(hs - (double)hi);
+    C.Hm[q] = hs;
     C.Hd[q] = hs * TWOM32;
   }
   double w[3];
   box_widths(C.H, w);
-  for (int q = 0; q < 3; ++q) C.nb[q] = max(1, (int)floor(w[q] / rcs));
+  for (int q = 0; q < 3; ++q) C.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / rcs)));
   // never exceed the bins allocated to this cell: coarser bins are still valid (>= rc + skin)
   while (C.nb[0] * C.nb[1] * C.nb[2] > max(C.bin_cap, 1)) {
     int q = 0;

@@ -252,9 +252,9 @@ void launch_build(rcell_ctx* c) {
   hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
   hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64), 0, c->stream, a,
                      (const int*)c->bin_cell);
-  const dim3 bl(TILE * LPA);
-  if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gt, bl, 0, c->stream, a);
-  else hipLaunchKernelGGL(k_build_list<Mixed>, gt, bl, 0, c->stream, a);
+  const dim3 gl(c->ntiles * (TILE / BUILD_ATOMS)), bl(BUILD_ATOMS * LPA);
+  if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gl, bl, 0, c->stream, a);
+  else hipLaunchKernelGGL(k_build_list<Mixed>, gl, bl, 0, c->stream, a);
 }
 
 void launch_start(rcell_ctx* c) {
@@ -359,6 +359,9 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
 
 int ensure_list_capacity(rcell_ctx* c, int need) {
   if (need <= c->maxnb) return RCELL_OK;
+  // the pair loops address the list with 32-bit element indices
+  if ((unsigned long long)need * (unsigned long long)c->npad >= (1ull << 32))
+    return fail(c, RCELL_ERR_OOM, "neighbour list would exceed 2^32 entries (16 GiB); split the batch");
   drop_graphs(c);
   dfree(c, c->nbr);
   c->nbr = nullptr;
