@@ -70,6 +70,7 @@ def lib():
             "orc_forces": [vp, vp, i32, vp, i32, vp, vp, vp, vp],
             "orc_create": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
             "orc_set_deformation": [vp, vp], "orc_run": [vp, i32], "orc_get_stress": [vp, vp, vp],
+            "orc_set_cell_ids": [vp, vp],
             "orc_get_status": [vp, vp], "orc_get_forces": [vp, i32, vp],
             "orc_get_state": [vp, i32, vp, vp, vp, vp, vp],
             "orc_set_state": [vp, i32, vp, vp, vp, vp, i64], "orc_get_energy": [vp, vp, vp],
@@ -169,7 +170,9 @@ class OracleBatch:
     """Batched r-cell context with the library's create / set_deformation / run / get_stress
     semantics, computed by the FP64 oracle."""
 
-    def __init__(self, params, cells):
+    def __init__(self, params, cells, cell_ids=None):
+        """cell_ids: the cells' indices in the Langevin noise counter (default 0..n-1), e.g. their
+        positions in a larger batch of which these cells are a sample."""
         self.params = dict(params)
         self._ps = params_struct(params)
         self.natoms = np.array([len(c["x"]) for c in cells], np.int32)
@@ -187,6 +190,12 @@ class OracleBatch:
         if st != OK:
             raise OracleError(st, "create")
         self._h = h
+        if cell_ids is not None:
+            ids = np.ascontiguousarray(cell_ids, np.int32)
+            assert len(ids) == self.ncells
+            st = lib().orc_set_cell_ids(self._h, _p(ids))
+            if st != OK:
+                raise OracleError(st, "set_cell_ids")
 
     def __del__(self):
         if getattr(self, "_h", None):

@@ -350,6 +350,7 @@ typedef struct {
   double wsum[6], last[6], pe;
   int64_t wcount;
   int32_t status;
+  int32_t id;          /* the cell's index in the Langevin noise counter (its batch position) */
   pairlist L;
 } ocell;
 
@@ -418,6 +419,7 @@ int orc_create(const orc_params* p, int32_t ncells, const int32_t* natoms, const
   for (int32_t k = 0; k < ncells && st == OK; ++k) {
     ocell* c = &C->c[k];
     c->n = natoms[k]; c->nb = nbonds[k];
+    c->id = k;
     if (c->n < 0 || c->nb < 0 || (c->nb > 0 && !bonds)) { st = E_ARG; break; }
     size_t bytes = (size_t)(c->n > 0 ? c->n : 1) * 3 * sizeof(double);
     c->x = (double*)malloc(bytes); c->v = (double*)calloc(1, bytes); c->f = (double*)calloc(1, bytes);
@@ -522,6 +524,14 @@ static int step_cell(const orc_params* p, ocell* c, int32_t cell_index) {
   return OK;
 }
 
+/* Give the cells other noise-counter indices (default: their position in this context), so that
+ * a few cells of a large batch, run here alone, draw the noise they draw inside that batch. */
+int orc_set_cell_ids(orc_ctx* C, const int32_t* ids) {
+  if (!C || !ids) return E_ARG;
+  for (int32_t k = 0; k < C->ncells; ++k) C->c[k].id = ids[k];
+  return OK;
+}
+
 int orc_run(orc_ctx* C, int32_t nsteps) {
   if (!C || nsteps < 0) return E_ARG;
   int st_all = OK;
@@ -529,7 +539,7 @@ int orc_run(orc_ctx* C, int32_t nsteps) {
   for (int32_t k = 0; k < C->ncells; ++k) {
     ocell* c = &C->c[k];
     for (int32_t s = 0; s < nsteps && c->status == OK; ++s) {
-      int st = step_cell(&C->p, c, k);
+      int st = step_cell(&C->p, c, c->id);
       if (st != OK) c->status = st;
     }
     if (c->status != OK) st_all = c->status;

@@ -32,3 +32,19 @@ def test_uniforms_are_uniform():
     hist, _ = np.histogram(u, bins=20, range=(0, 1))
     chi2 = ((hist - len(u) / 20) ** 2 / (len(u) / 20)).sum()
     assert chi2 < 45.3   # 19 dof, p ~ 0.999
+
+
+def test_cell_ids_select_the_noise_stream():
+    # a cell run alone with its batch index as noise id follows exactly the trajectory it has
+    # inside the batch; with another id it draws other noise
+    from synth import configs
+    cells = [configs.kg_cell([20] * 10, 40 + k) for k in range(3)]
+    p = configs.kg_params(precision="fp64")
+    full = core.OracleBatch(p, cells)
+    alone = core.OracleBatch(p, [cells[2]], cell_ids=[2])
+    other = core.OracleBatch(p, [cells[2]])
+    for b in (full, alone, other):
+        b.run(5)
+    xf = full.get_state(2)["x"]
+    assert np.array_equal(alone.get_state(0)["x"], xf)
+    assert not np.array_equal(other.get_state(0)["x"], xf)
