@@ -468,6 +468,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=25)
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0 = autotune)")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="neighbour skin override for the MD workloads (changes speed, never the pairs within rc)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -492,7 +494,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.skin is not None:
+        for name in ("kg_params", "cu_params"):
+            base = getattr(configs, name)
+            setattr(configs, name, (lambda b: lambda **over: dict(b(**over), skin=args.skin))(base))
     out = WORKLOADS[args.workload](args, torch, rcell, configs)
+    if args.skin is not None:
+        out["config"]["skin"] = args.skin
     print(json.dumps(out), flush=True)
 
 

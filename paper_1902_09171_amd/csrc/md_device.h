@@ -10,7 +10,11 @@
 //               image shifts and no FP64 arithmetic (d = H dS, H as a float hi + lo pair).
 //   sb          s at the last neighbour build (displacement check)
 //   nbr         Verlet list within rc + skin, column-major nbr[k * npad + i], cell-local j
-//   bond        up to four FENE partners per atom (cell-local, -1 = none)
+//   bond        up to four FENE partners per atom (cell-local positions, -1 = none)
+//   gid         original cell-local index of the atom stored at each position; pos_of inverts it;
+//               bond0 holds the partners by original index.  At every neighbour build a cell's
+//               atoms are reordered by (bin, original index), so that neighbours sit close in
+//               memory; everything that identifies an atom (noise counter, host API order) uses gid.
 // Work is distributed over 64-atom tiles (a tile never straddles two cells); each tile writes
 // one partial record and a per-cell kernel reduces them in a fixed order (deterministic).
 #pragma once
@@ -52,6 +56,10 @@ struct CellDev {
 
 struct Tile { int cell, begin, count, pad; };
 
+// Tile-grid kernels: block w works on tile w (the grid has exactly ntiles blocks).
+__host__ __device__ inline int tile_grid(int ntiles) { return ntiles; }
+__device__ __forceinline__ int block_tile(int ntiles, int block) { return block; }
+
 struct Part {                     // one tile's contribution
   double W[6], K[6], pe, pad;
   long long xi[3];
@@ -70,7 +78,11 @@ struct MDArgs {
   double *x, *y, *z, *vx, *vy, *vz;
   void *fx, *fy, *fz;
   void *s_cur, *s_nxt, *sb;
-  const int4* bond;
+  int4* bond;
+  const int4* bond0;
+  int* gid;
+  int* pos_of;
+  char* pscr;                      // reorder scratch: 6 doubles, one S and two ints per atom (npad rows)
   int* nn;
   int* nbr;
   long long npad;
@@ -341,7 +353,7 @@ template <class P>
 __device__ __forceinline__ void atom_tail(const MDArgs& a, const CellDev& C, int cell, long long i,
                                           double fcx, double fcy, double fcz, int mode, TailOut& o) {
   double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
-  const int gid = (int)(i - C.off);
+  const int gid = a.gid[i];
   double f0 = fcx, f1 = fcy, f2 = fcz;
   if (mode == MODE_PRIME) {
     // forces after create / deformation / restore: conservative part only; v is a full-step velocity
@@ -418,7 +430,7 @@ struct PartShared {
 // Reduce one tile's contributions (every thread of the block calls this) and write its Part:
 // a wave-level shuffle reduction, then thread 0 adds the NW wave results in order.
 template <int NT>
-__device__ __forceinline__ void write_part(Part* parts, const double W[6], const double K[6], double pe,
+__device__ __forceinline__ void write_part(Part* parts, int part, const double W[6], const double K[6], double pe,
                                            const long long xi[3], float maxd2, int status,
                                            PartShared<NT / 64>& sh) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
@@ -438,7 +450,7 @@ __device__ __forceinline__ void write_part(Part* parts, const double W[6], const
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    Part& p = parts[blockIdx.x];
+    Part& p = parts[part];
     double acc[13];
     long long la[3] = {0, 0, 0};
     float mm = 0.f;
@@ -488,7 +500,9 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
   __shared__ PartShared<NT / 64> psh;
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
   const bool skip = (mode == MODE_PRIME && !C.pending);
@@ -565,14 +579,16 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
     maxd2 = o.maxd2;
   }
-  write_part<NT>(a.parts, W, K, PE, xi, maxd2, status, psh);
+  write_part<NT>(a.parts, tb, W, K, PE, xi, maxd2, status, psh);
 }
 
 // Sutton-Chen pass 1: host density rho_i and F'(rho_i) = -eps c / (2 sqrt(rho_i)), stored in s.w
 template <class P, int TPA, int SN, int SM>
 __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   using R = typename P::R;
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
   const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending);
@@ -612,7 +628,9 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
   __shared__ PartShared<NT / 64> psh;
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
   const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending);
@@ -674,14 +692,16 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
     maxd2 = o.maxd2;
   }
-  write_part<NT>(a.parts, W, K, PE, xi, maxd2, 0, psh);
+  write_part<NT>(a.parts, tb, W, K, PE, xi, maxd2, 0, psh);
 }
 
 // First half kick and drift of a run (the remaining ones are fused into the force kernels).
 template <class P>
 __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
   __shared__ PartShared<1> psh;
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const long long i = (long long)t.begin + threadIdx.x;
   long long xi[3] = {0, 0, 0};
@@ -701,12 +721,12 @@ __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
     maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     if (a.gamma_on) {
       int k[3];
-      noise_units(a, (int)(i - C.off), t.cell, C.step + 1, k);
+      noise_units(a, a.gid[i], t.cell, C.step + 1, k);
       xi[0] = k[0]; xi[1] = k[1]; xi[2] = k[2];
     }
   }
   const double Z[6] = {0, 0, 0, 0, 0, 0};
-  write_part<TILE>(a.parts, Z, Z, 0.0, xi, maxd2, 0, psh);
+  write_part<TILE>(a.parts, tb, Z, Z, 0.0, xi, maxd2, 0, psh);
 }
 
 // Per-cell reduction of the tile partials: one wave per cell, each lane sums every 64th tile
@@ -782,7 +802,9 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
 //                and the force sums built from them are deterministic
 template <class P>
 __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild || (int)threadIdx.x >= t.count) return;
   const long long i = (long long)t.begin + threadIdx.x;
@@ -844,7 +866,9 @@ __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
 }
 
 __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild || (int)threadIdx.x >= t.count) return;
   const long long i = (long long)t.begin + threadIdx.x;
@@ -854,18 +878,20 @@ __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
 
-// one lane per bin slot of every cell (grid over the bin capacity), one wave per block.  When the
-// wave's 64 bins fit in LDS together they are staged there and every lane rank-sorts its own bin
-// (entry v goes to position #{entries < v}; atom indices are distinct) straight back to memory.
-// Otherwise bins of up to SMALL_BIN atoms are insertion-sorted by their lane and larger bins are
-// rank-sorted by the whole wave, one after another, through the scratch array.
+// one lane per bin slot of every cell (grid over the bin capacity), one wave per block.  Each bin
+// is ordered by the original index (gid) of its atoms, so that the reorder that follows depends
+// only on positions, not on earlier reorders.  When the wave's 64 bins fit in the cap keys of
+// dynamic LDS (sized by the host from the expected bin occupancy) their keys are staged there and every lane rank-sorts its own bin (key v goes to position
+// #{keys < v}; keys are distinct); otherwise bins of up to SMALL_BIN atoms are insertion-sorted by
+// their lane and larger bins are rank-sorted by the whole wave, one after another, through the
+// scratch array.  Sorted keys are mapped back to current cell-local indices through pos_of.
 constexpr int SMALL_BIN = 24;
-constexpr int SORT_LDS = 8192;       // staged entries per wave (32 KB)
-__global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) {
-  __shared__ int stage[SORT_LDS];
+constexpr int SORT_LDS_MAX = 16384;  // staged keys per wave at most (64 KB)
+__global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell, int cap) {
+  extern __shared__ int stage[];
   const long long g = (long long)blockIdx.x * 64 + threadIdx.x;
   int big = 0;                       // this lane's bin needs the wave
-  int *p = nullptr, n = 0;
+  int *p = nullptr, n = 0, off = 0;
   if (g < a.bins_total) {
     const int c = bin_cell[g];
     const CellDev& C = a.cells[c];
@@ -873,6 +899,7 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
     if (C.rebuild && b < C.nb[0] * C.nb[1] * C.nb[2]) {
       p = a.binned + C.off + a.bstart[g];
       n = a.bnum[g];
+      off = C.off;
     }
   }
   int incl = n;                      // exclusive offsets of the 64 bins in the staging array
@@ -883,18 +910,19 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
   }
   const int total = __shfl(incl, 63);
   if (total == 0) return;
-  if (total <= SORT_LDS) {
-    int* sb = stage + (incl - n);
-    for (int e = 0; e < n; ++e) sb[e] = p[e];
+  if (total <= cap) {
+    int* sk = stage + (incl - n);
+    for (int e = 0; e < n; ++e) sk[e] = a.gid[off + p[e]];
     __syncthreads();
     for (int e = 0; e < n; ++e) {
-      const int v = sb[e];
+      const int v = sk[e];
       int rank = 0;
-      for (int q = 0; q < n; ++q) rank += sb[q] < v;
-      p[rank] = v;
+      for (int q = 0; q < n; ++q) rank += sk[q] < v;
+      p[rank] = a.pos_of[off + v];
     }
     return;
   }
+  for (int e = 0; e < n; ++e) p[e] = a.gid[off + p[e]];     // sort keys in place
   big = n > SMALL_BIN;
   if (!big)
     for (int u = 1; u < n; ++u) {
@@ -903,6 +931,8 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
       while (q >= 0 && p[q] > v) { p[q + 1] = p[q]; --q; }
       p[q + 1] = v;
     }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
   // large bins, one after another, by all 64 lanes
   unsigned long long mask = __ballot(big);
   while (mask) {
@@ -910,7 +940,6 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
     mask &= mask - 1;
     int* pb = (int*)__shfl((long long)(size_t)p, src);
     const int m = __shfl(n, src);
-    const long long gb = __shfl(g, src);
     int* tmp = a.sort_tmp + (pb - a.binned);
     for (int e = threadIdx.x; e < m; e += 64) {
       const int v = pb[e];
@@ -921,23 +950,108 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell) 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     for (int e = threadIdx.x; e < m; e += 64) pb[e] = tmp[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
-    (void)gb;
   }
+  for (int e = 0; e < n; ++e) p[e] = a.pos_of[off + p[e]];  // keys back to current indices
 }
 
-// Verlet list of every atom: cell-local j with |d| < rc + skin over the 27 (distinct) neighbour
-// bins.  LPA lanes share one atom and lane l scans bin l, so the dependent loads of a bin (its
-// range, its atom indices, their positions) are the only latency chain.  Each lane counts its
-// neighbours, an exclusive scan over the lanes gives its offset, and a second scan writes them:
-// the list order (bin by bin, ascending index inside a bin) is deterministic.  A block covers
-// BUILD_ATOMS atoms, so TILE / BUILD_ATOMS blocks cover one tile.
+// Reorder the atoms of every rebuilding cell by (bin, original index): position q of the cell
+// receives the atom binned[q].  Phase 1 gathers positions, velocities, the fixed-point coordinates,
+// bin coordinates and original indices into the scratch rows and records pos_of; phase 2 copies
+// them back (also as the build reference) and rewrites the bond partners from bond0 through pos_of.
+// The stored total force is not moved: the prime or last step of the run writes it afterwards.
+template <class P>
+struct Reorder {
+  double *x, *y, *z, *vx, *vy, *vz;
+  typename P::S* s;
+  int *abin, *gid;
+  __device__ explicit Reorder(const MDArgs& a) {
+    const long long np = a.npad;
+    x = (double*)a.pscr; y = x + np; z = y + np; vx = z + np; vy = vx + np; vz = vy + np;
+    s = (typename P::S*)(vz + np);
+    abin = (int*)(s + np); gid = abin + np;
+  }
+};
+
+template <class P>
+__global__ __launch_bounds__(TILE) void k_reorder_gather(MDArgs a) {
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  const long long q = (long long)t.begin + threadIdx.x;
+  const long long src = C.off + a.binned[q];
+  const Reorder<P> r(a);
+  r.x[q] = a.x[src]; r.y[q] = a.y[src]; r.z[q] = a.z[src];
+  r.vx[q] = a.vx[src]; r.vy[q] = a.vy[src]; r.vz[q] = a.vz[src];
+  r.s[q] = P::load(a.s_cur, src);
+  r.abin[q] = a.abin[src];
+  const int g = a.gid[src];
+  r.gid[q] = g;
+  a.pos_of[C.off + g] = (int)(q - C.off);
+}
+
+template <class P>
+__global__ __launch_bounds__(TILE) void k_reorder_scatter(MDArgs a) {
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  const long long q = (long long)t.begin + threadIdx.x;
+  const Reorder<P> r(a);
+  a.x[q] = r.x[q]; a.y[q] = r.y[q]; a.z[q] = r.z[q];
+  a.vx[q] = r.vx[q]; a.vy[q] = r.vy[q]; a.vz[q] = r.vz[q];
+  const typename P::S sq = r.s[q];
+  P::store_xyz(a.s_cur, q, sq);
+  P::store_xyz(a.sb, q, sq);
+  a.abin[q] = r.abin[q];
+  const int g = r.gid[q];
+  a.gid[q] = g;
+  const int4 b0 = a.bond0[C.off + g];
+  int4 b;
+  b.x = b0.x < 0 ? -1 : a.pos_of[C.off + b0.x];
+  b.y = b0.y < 0 ? -1 : a.pos_of[C.off + b0.y];
+  b.z = b0.z < 0 ? -1 : a.pos_of[C.off + b0.z];
+  b.w = b0.w < 0 ? -1 : a.pos_of[C.off + b0.w];
+  a.bond[q] = b;
+}
+
+// Original order for the atoms of cells [first, first + count) (create, set_state): gid and
+// pos_of the identity, bonds as given.  Grid over all tiles.
+__global__ __launch_bounds__(TILE) void k_reset_order(MDArgs a, int first, int count) {
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  if (t.cell < first || t.cell >= first + count || (int)threadIdx.x >= t.count) return;
+  const long long i = (long long)t.begin + threadIdx.x;
+  const int li = (int)(i - a.cells[t.cell].off);
+  a.gid[i] = li;
+  a.pos_of[i] = li;
+  a.bond[i] = a.bond0[i];
+}
+
+// Verlet list of every atom (after the reorder, so positions are in bin order): cell-local j with
+// |d| < rc + skin over the 27 (distinct) neighbour bins.  LPA lanes share one atom; lane l scans
+// bins l, l + LPA, ..., each a contiguous range of positions, and keeps its first STASH accepted
+// neighbours in LDS while counting all of them.  An exclusive scan over the lanes gives each lane's
+// offset; the stashed entries are then written out, and only an atom with a lane that accepted
+// more than STASH scans its bins a second time, writing directly.  The list order (lane-major over
+// bins, ascending position inside a bin) is deterministic either way.  A block covers BUILD_ATOMS
+// atoms, so TILE / BUILD_ATOMS blocks cover one tile.
 constexpr int LPA = 8;
 constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
+constexpr int STASH = 8;
 template <class P>
 __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
   constexpr int PER_TILE = TILE / BUILD_ATOMS;
-  const Tile t = a.tiles[blockIdx.x / PER_TILE];
+  constexpr int NT = BUILD_ATOMS * LPA;
+  __shared__ int stash[STASH * NT];          // entry e of thread t at stash[e * NT + t]
+  const int tb = block_tile(a.ntiles, blockIdx.x / PER_TILE);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild) return;
   const int slot = (blockIdx.x % PER_TILE) * BUILD_ATOMS + threadIdx.x / LPA, lane = threadIdx.x % LPA;
@@ -967,9 +1081,9 @@ __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
   const int nq = cnt[0] * cnt[1] * cnt[2];
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
-  int n = 0, base = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    int k = base;
+  const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
+  // visit this lane's neighbours in list order
+  auto scan_bins = [&](auto&& take) {
     for (int q = lane; q < nq && active; q += LPA) {
       int u0, u1, u2;
       if (full) {                               // division by constants
@@ -978,39 +1092,50 @@ __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
         u0 = q / (cnt[1] * cnt[2]); u1 = (q / cnt[2]) % cnt[1]; u2 = q % cnt[2];
       }
       const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
-      const int* p = a.binned + C.off + a.bstart[C.bin_off + b];
+      // the atoms are in bin order: bin b holds the consecutive positions bstart .. bstart + m - 1
+      const int p0 = a.bstart[C.bin_off + b];
       const int m = a.bnum[C.bin_off + b];
-      for (int e0 = 0; e0 < m; e0 += UNR) {     // UNR candidates in flight, kept in bin order
-        int lj[UNR];
+      for (int e0 = 0; e0 < m; e0 += UNR) {     // UNR candidates in flight
         typename P::S sj[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) lj[u] = e0 + u < m ? p[e0 + u] : -1;
-#pragma unroll
-        for (int u = 0; u < UNR; ++u)
-          if (lj[u] >= 0) sj[u] = P::load(a.s_cur, C.off + lj[u]);
+        for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, p0 + min(e0 + u, m - 1));
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-          if (lj[u] < 0 || lj[u] == li) continue;
+          const int lj = p0 + e0 + u;
+          if (e0 + u >= m || lj == li) continue;
           typename P::R d[3];
           P::sep(sj[u], si, g, d);
-          if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
-            if (pass == 1 && k < a.maxnb) a.nbr[(long long)k * a.npad + i] = lj[u];
-            ++k;
-          }
+          if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) take(lj);
         }
       }
     }
-    if (pass == 0) {
-      n = k;                                  // this lane's count
-      int incl = n;                           // inclusive scan over the LPA lanes of the atom
+  };
+  int mine = 0;
+  scan_bins([&](int lj) {
+    if (mine < STASH) stash[mine * NT + threadIdx.x] = lj;
+    ++mine;
+  });
+  int incl = mine;                            // inclusive scan over the LPA lanes of the atom
 #pragma unroll
-      for (int o = 1; o < LPA; o <<= 1) {
-        const int v = __shfl_up(incl, o, LPA);
-        if (lane >= o) incl += v;
-      }
-      base = incl - n;
-      n = __shfl(incl, LPA - 1, LPA);          // total for the atom
-    }
+  for (int o = 1; o < LPA; o <<= 1) {
+    const int v = __shfl_up(incl, o, LPA);
+    if (lane >= o) incl += v;
+  }
+  const int base = incl - mine;
+  int n = __shfl(incl, LPA - 1, LPA);         // total for the atom
+  int over = mine > STASH ? 1 : 0;            // does any lane of the atom need a second scan
+#pragma unroll
+  for (int o = 1; o < LPA; o <<= 1) over |= __shfl_xor(over, o, LPA);
+  const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
+  if (!over) {
+    for (int e = 0; e < mine; ++e)
+      if (base + e < a.maxnb) a.nbr[(unsigned)(base + e) * np + ii] = stash[e * NT + threadIdx.x];
+  } else {
+    int k = base;
+    scan_bins([&](int lj) {
+      if (k < a.maxnb) a.nbr[(unsigned)k * np + ii] = lj;
+      ++k;
+    });
   }
   if (active && lane == 0) {
     if (n > a.maxnb) {
@@ -1176,7 +1301,9 @@ __global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double 
 // to rounding: the remap leaves S = H^-1 x unchanged)
 template <class P>
 __global__ __launch_bounds__(TILE) void k_remap(MDArgs a, const Stage* st) {
-  const Tile t = a.tiles[blockIdx.x];
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
   if ((int)threadIdx.x >= t.count) return;
   const double* d = st[t.cell].dR;
   const long long i = (long long)t.begin + threadIdx.x;

@@ -36,11 +36,15 @@ struct rcell_ctx {
   std::string err;
   std::vector<int> off, n, tile_off, ntile, bin_off, bin_cap;
   long long bins_total = 0, bins_alloc = 0;
+  std::vector<double> occ;        // expected atoms per bin of each cell
+  int sort_cap = 256;             // keys staged in LDS per wave by the bin sort
   // device memory
   double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
   void *fx = nullptr, *fy = nullptr, *fz = nullptr;
   void *s[2] = {nullptr, nullptr}, *sb = nullptr;
-  int4* bond = nullptr;
+  int4 *bond = nullptr, *bond0 = nullptr;
+  int *gid = nullptr, *pos_of = nullptr;
+  char* pscr = nullptr;           // reorder scratch rows
   int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr, *sort_tmp = nullptr;
   int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
   CellDev* cells = nullptr;
@@ -66,6 +70,19 @@ namespace {
 void drop_graphs(rcell_ctx* c) {
   for (int q = 0; q < 2; ++q)
     if (c->graph[q]) { (void)hipGraphExecDestroy(c->graph[q]); c->graph[q] = nullptr; }
+}
+
+// the bin sort stages twice the expected keys of its 64 bins in LDS (a fuller wave falls back to
+// the slower paths); a change of that size invalidates the captured graphs
+void set_occupancy(rcell_ctx* c, int cell, double atoms_per_bin) {
+  c->occ[cell] = atoms_per_bin;
+  double m = 0.0;
+  for (double o : c->occ) m = std::max(m, o);
+  const int cap = (int)std::min<double>(SORT_LDS_MAX, std::max(256.0, 2.0 * 64.0 * std::ceil(m) + 64.0));
+  if (cap != c->sort_cap) {
+    drop_graphs(c);
+    c->sort_cap = cap;
+  }
 }
 
 int fail(rcell_ctx* c, int code, const std::string& msg) {
@@ -117,6 +134,25 @@ double width_min(const double H[9]) {   // host-side validation of a box against
   return w;
 }
 
+// host twin of the device's bin count: floor of each perpendicular width over rc + skin
+int bins_exact(const double H[9], double rcs) {
+  auto col = [&](int k, double v[3]) { v[0] = H[k]; v[1] = H[3 + k]; v[2] = H[6 + k]; };
+  double a[3][3];
+  for (int k = 0; k < 3; ++k) col(k, a[k]);
+  const double V = std::fabs(a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                             a[1][0] * (a[0][1] * a[2][2] - a[0][2] * a[2][1]) +
+                             a[2][0] * (a[0][1] * a[1][2] - a[0][2] * a[1][1]));
+  long long nb = 1;
+  for (int k = 0; k < 3; ++k) {
+    const double* u = a[(k + 1) % 3];
+    const double* v = a[(k + 2) % 3];
+    const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+    const double w = V / std::sqrt(cx * cx + cy * cy + cz * cz);
+    nb *= std::min(BIN_MASK, std::max(1, (int)std::floor(w / rcs)));
+  }
+  return (int)std::min<long long>(nb, 1 << 30);
+}
+
 int bins_for(const double H[9], double rcs) {
   // an upper bound on floor(w0/rcs) floor(w1/rcs) floor(w2/rcs): V / rcs^3
   const double V = H[0] * H[4] * H[8];
@@ -133,7 +169,8 @@ MDArgs make_args(const rcell_ctx* c) {
   a.x = c->x; a.y = c->y; a.z = c->z; a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
   a.s_cur = c->s[c->cur]; a.s_nxt = c->s[1 - c->cur]; a.sb = c->sb;
-  a.bond = c->bond; a.nn = c->nn; a.nbr = c->nbr; a.npad = c->npad; a.maxnb = c->maxnb;
+  a.bond = c->bond; a.bond0 = c->bond0; a.gid = c->gid; a.pos_of = c->pos_of; a.pscr = c->pscr;
+  a.nn = c->nn; a.nbr = c->nbr; a.npad = c->npad; a.maxnb = c->maxnb;
   a.cells = c->cells; a.tiles = c->tiles; a.parts = c->parts; a.ntiles = c->ntiles; a.ncells = c->ncells;
   a.abin = c->abin; a.bcount = c->bcount; a.bstart = c->bstart; a.bnum = c->bnum; a.bfill = c->bfill;
   a.binned = c->binned;
@@ -200,7 +237,7 @@ struct ProfScope {
 
 template <class P, int TPA, int SN, int SM>
 void force_eam_t(rcell_ctx* c, const MDArgs& a, int mode) {
-  const dim3 grid(c->ntiles), block(TILE * TPA);
+  const dim3 grid(tile_grid(c->ntiles)), block(TILE * TPA);
   {
     ProfScope ps(c, 1);
     hipLaunchKernelGGL((k_eam_rho<P, TPA, SN, SM>), grid, block, 0, c->stream, a, mode);
@@ -213,7 +250,7 @@ template <class P, int TPA>
 void force_t(rcell_ctx* c, const MDArgs& a, int mode) {
   if (c->p.potential == RCELL_POT_KG) {
     ProfScope ps(c, 0);
-    hipLaunchKernelGGL((k_force_kg<P, TPA>), dim3(c->ntiles), dim3(TILE * TPA), 0, c->stream, a, mode);
+    hipLaunchKernelGGL((k_force_kg<P, TPA>), dim3(tile_grid(c->ntiles)), dim3(TILE * TPA), 0, c->stream, a, mode);
   } else if (a.sc_n == 9 && a.sc_m == 6) {      // copper, nickel: exponents fixed at compile time
     force_eam_t<P, TPA, 9, 6>(c, a, mode);
   } else {
@@ -245,22 +282,29 @@ void launch_reduce(rcell_ctx* c, int mode) {
 
 void launch_build(rcell_ctx* c) {
   const MDArgs a = make_args(c);
-  const dim3 gt(c->ntiles), bt(TILE), gc(c->ncells), bc(SCAN_NT);
+  const dim3 gt(tile_grid(c->ntiles)), bt(TILE), gc(c->ncells), bc(SCAN_NT);
   if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gt, bt, 0, c->stream, a);
   else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
   hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
   hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
-  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64), 0, c->stream, a,
-                     (const int*)c->bin_cell);
-  const dim3 gl(c->ntiles * (TILE / BUILD_ATOMS)), bl(BUILD_ATOMS * LPA);
+  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64),
+                     sizeof(int) * c->sort_cap, c->stream, a, (const int*)c->bin_cell, c->sort_cap);
+  if (c->fp64) {
+    hipLaunchKernelGGL(k_reorder_gather<FP64>, gt, bt, 0, c->stream, a);
+    hipLaunchKernelGGL(k_reorder_scatter<FP64>, gt, bt, 0, c->stream, a);
+  } else {
+    hipLaunchKernelGGL(k_reorder_gather<Mixed>, gt, bt, 0, c->stream, a);
+    hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gt, bt, 0, c->stream, a);
+  }
+  const dim3 gl(tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)), bl(BUILD_ATOMS * LPA);
   if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gl, bl, 0, c->stream, a);
   else hipLaunchKernelGGL(k_build_list<Mixed>, gl, bl, 0, c->stream, a);
 }
 
 void launch_start(rcell_ctx* c) {
   const MDArgs a = make_args(c);
-  if (c->fp64) hipLaunchKernelGGL(k_start<FP64>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a);
-  else hipLaunchKernelGGL(k_start<Mixed>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a);
+  if (c->fp64) hipLaunchKernelGGL(k_start<FP64>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a);
+  else hipLaunchKernelGGL(k_start<Mixed>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a);
 }
 
 // neighbour build + conservative forces for every cell flagged pending
@@ -401,6 +445,7 @@ int deformation_common(rcell_ctx* c, const double* F_dev) {
   bool grow = false;
   for (int k = 0; k < nc; ++k) {
     need[k] = st[k].nbins;
+    set_occupancy(c, k, (double)c->n[k] / std::max(1, st[k].nbins));
     grow = grow || need[k] > c->bin_cap[k];
     dens = std::max(dens, st[k].density);
   }
@@ -412,8 +457,8 @@ int deformation_common(rcell_ctx* c, const double* F_dev) {
   hipLaunchKernelGGL(k_qr_commit, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, c->stage, nc, c->p.rc,
                      rcs, relist);
   const MDArgs a = make_args(c);
-  if (c->fp64) hipLaunchKernelGGL(k_remap<FP64>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a, c->stage);
-  else hipLaunchKernelGGL(k_remap<Mixed>, dim3(c->ntiles), dim3(TILE), 0, c->stream, a, c->stage);
+  if (c->fp64) hipLaunchKernelGGL(k_remap<FP64>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a, c->stage);
+  else hipLaunchKernelGGL(k_remap<Mixed>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a, c->stage);
   return prime(c);
 }
 
@@ -481,6 +526,8 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
   c->N = N;
   c->npad = (N + 63) / 64 * 64;
   c->ntiles = ntiles;
+  c->occ.assign(ncells, 0.0);
+  for (int k = 0; k < ncells; ++k) set_occupancy(c, k, (double)cells[k].natoms / bins_exact(cells[k].H0, rcs));
 
   // ---- stream and memory
   if (hip_stream) {
@@ -497,7 +544,10 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
   if ((e = dalloc(c, &c->x, N)) || (e = dalloc(c, &c->y, N)) || (e = dalloc(c, &c->z, N)) ||
       (e = dalloc(c, &c->vx, N)) || (e = dalloc(c, &c->vy, N)) || (e = dalloc(c, &c->vz, N)) ||
       (e = dalloc(c, &f0, 3 * fsz * N)) || (e = dalloc(c, &s0, ssz * N)) || (e = dalloc(c, &s1, ssz * N)) ||
-      (e = dalloc(c, &sbp, ssz * N)) || (e = dalloc(c, &c->bond, N)) || (e = dalloc(c, &c->nn, N)) ||
+      (e = dalloc(c, &sbp, ssz * N)) || (e = dalloc(c, &c->bond, N)) || (e = dalloc(c, &c->bond0, N)) ||
+      (e = dalloc(c, &c->gid, N)) || (e = dalloc(c, &c->pos_of, N)) ||
+      (e = dalloc(c, &c->pscr, (6 * sizeof(double) + ssz + 2 * sizeof(int)) * (size_t)c->npad)) ||
+      (e = dalloc(c, &c->nn, N)) ||
       (e = dalloc(c, &c->abin, N)) || (e = dalloc(c, &c->binned, N)) || (e = dalloc(c, &c->sort_tmp, N)) ||
       (e = dalloc(c, &c->cells, ncells)) || (e = dalloc(c, &c->tiles, ntiles)) || (e = dalloc(c, &c->parts, ntiles)) ||
       (e = dalloc(c, &c->stage, ncells)) || (e = dalloc(c, &c->dscratch, (size_t)17 * ncells)) || (e = dalloc(c, &c->dscratch2, (size_t)6 * ncells)) ||
@@ -553,13 +603,14 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
       hipMemcpyAsync(c->vx, hvx.data(), nb, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->vy, hvy.data(), nb, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->vz, hvz.data(), nb, hipMemcpyHostToDevice, c->stream) ||
-      hipMemcpyAsync(c->bond, hb.data(), sizeof(int4) * N, hipMemcpyHostToDevice, c->stream) ||
+      hipMemcpyAsync(c->bond0, hb.data(), sizeof(int4) * N, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->tiles, tl.data(), sizeof(Tile) * ntiles, hipMemcpyHostToDevice, c->stream) ||
       hipMemcpyAsync(c->cells, hc.data(), sizeof(CellDev) * ncells, hipMemcpyHostToDevice, c->stream) ||
       hipMemsetAsync(f0, 0, 3 * fsz * N, c->stream) || hipMemsetAsync(s0, 0, ssz * N, c->stream) ||
       hipMemsetAsync(s1, 0, ssz * N, c->stream) || hipStreamSynchronize(c->stream))
     return bail(fail(c, RCELL_ERR_DEVICE, "initial upload failed"));
   if ((e = layout_bins(c, need_bins))) return bail(e);
+  hipLaunchKernelGGL(k_reset_order, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, make_args(c), 0, ncells);
   hipLaunchKernelGGL(k_set_box, dim3((ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, ncells, rcs);
   if ((e = prime(c))) return bail(e);
   Gathered g;
@@ -697,13 +748,15 @@ int rcell_get_forces(rcell_ctx* c, int32_t cell, double* f) {
   const long long o = c->off[cell], n = c->n[cell];
   const size_t fsz = sizeof(double);
   std::vector<char> buf(3 * fsz * n);
+  std::vector<int> ids(n);
   void* src[3] = {c->fx, c->fy, c->fz};
   for (int q = 0; q < 3; ++q)
     HIPCHK(c, hipMemcpyAsync(buf.data() + q * fsz * n, (char*)src[q] + fsz * o, fsz * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ids.data(), c->gid + o, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (int q = 0; q < 3; ++q)
-    for (long long i = 0; i < n; ++i)
-      f[3 * i + q] = ((const double*)buf.data())[q * n + i];
+    for (long long i = 0; i < n; ++i)                // position i holds original atom ids[i]
+      f[3 * (long long)ids[i] + q] = ((const double*)buf.data())[q * n + i];
   return RCELL_OK;
 }
 
@@ -712,15 +765,17 @@ int rcell_get_state(rcell_ctx* c, int32_t cell, double* x, double* v, double* H,
   const long long o = c->off[cell], n = c->n[cell];
   std::vector<double> buf(6 * n);
   double* src[6] = {c->x, c->y, c->z, c->vx, c->vy, c->vz};
+  std::vector<int> ids(n);
   for (int q = 0; q < 6; ++q)
     HIPCHK(c, hipMemcpyAsync(buf.data() + q * n, src[q] + o, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ids.data(), c->gid + o, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
   CellDev C;
   HIPCHK(c, hipMemcpyAsync(&C, c->cells + cell, sizeof(CellDev), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (long long i = 0; i < n; ++i)
+  for (long long i = 0; i < n; ++i)                  // position i holds original atom ids[i]
     for (int q = 0; q < 3; ++q) {
-      if (x) x[3 * i + q] = buf[q * n + i];
-      if (v) v[3 * i + q] = buf[(3 + q) * n + i];
+      if (x) x[3 * (long long)ids[i] + q] = buf[q * n + i];
+      if (v) v[3 * (long long)ids[i] + q] = buf[(3 + q) * n + i];
     }
   if (H) std::memcpy(H, C.H, sizeof(C.H));
   if (Rprev) std::memcpy(Rprev, C.Rprev, sizeof(C.Rprev));
@@ -739,6 +794,7 @@ int rcell_set_state(rcell_ctx* c, int32_t cell, const double* x, const double* v
   const long long o = c->off[cell], n = c->n[cell];
   std::vector<int> need(c->bin_cap);
   need[cell] = std::max(need[cell], bins_for(H, rcs));
+  set_occupancy(c, cell, (double)n / bins_exact(H, rcs));
   int e;
   if (need[cell] > c->bin_cap[cell] && (e = layout_bins(c, need))) return e;
   if ((e = ensure_list_capacity(c, list_capacity(n / (H[0] * H[4] * H[8]), rcs)))) return e;
@@ -756,6 +812,8 @@ int rcell_set_state(rcell_ctx* c, int32_t cell, const double* x, const double* v
   C.step = step;
   C.status = 0;
   HIPCHK(c, hipMemcpyAsync(c->cells + cell, &C, sizeof(CellDev), hipMemcpyHostToDevice, c->stream));
+  // the state arrives in original order: identity order, then the rebuild reorders the cell
+  hipLaunchKernelGGL(k_reset_order, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, make_args(c), cell, 1);
   hipLaunchKernelGGL(k_set_box, dim3(1), dim3(64), 0, c->stream, c->cells, cell, 1, rcs);
   if ((e = prime(c))) return e;
   HIPCHK(c, hipStreamSynchronize(c->stream));
