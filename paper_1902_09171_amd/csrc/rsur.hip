@@ -29,6 +29,8 @@ struct rsur_ctx {
   std::string err;
   float *p = nullptr, *g = nullptr, *m1 = nullptr, *m2 = nullptr;   // K x P
   bf16* pb = nullptr;                                               // K x P (weights used)
+  bf16* pbt = nullptr;                                              // K x P, weights transposed
+  bool pbt_stale = true;                                            // pbt behind pb
   std::vector<bf16*> act;                    // act[l]: K x Mp x dp[l] (act[0] shared: Mp x dp[0])
   std::vector<float*> Z;                     // Z[l]: K x Mp x dp[l + 1], hidden layers
   float* out = nullptr;                      // K x Mp x dp[L]
@@ -159,7 +161,7 @@ int rsur_create(int32_t din, int32_t width, int32_t depth, int32_t dout, int32_t
   const long long KP = (long long)c->K * c->P;
   int e;
   if ((e = ralloc(c, &c->p, KP)) || (e = ralloc(c, &c->g, KP)) || (e = ralloc(c, &c->m1, KP)) ||
-      (e = ralloc(c, &c->m2, KP)) || (e = ralloc(c, &c->pb, KP)))
+      (e = ralloc(c, &c->m2, KP)) || (e = ralloc(c, &c->pb, KP)) || (e = ralloc(c, &c->pbt, KP)))
     return bail(e);
   c->act.resize(c->L);
   c->Z.resize(std::max(c->L - 1, 0));
@@ -222,6 +224,7 @@ int rsur_set_params(rsur_ctx* c, int32_t member, const float* w) {
                      c->pb + off, c->P);
   RCHK(c, hipStreamSynchronize(c->stream));
   c->t[member] = 0;
+  c->pbt_stale = true;
   return RCELL_OK;
 }
 
@@ -266,12 +269,40 @@ int rsur_fit_norm(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t n) 
   return RCELL_OK;
 }
 
+// inference: every layer in one fused kernel when the padded widths allow it and the batch gives
+// enough (row block, member) pairs to fill the GPU; small batches run layer by layer, whose
+// per-layer grids spread the same work over more blocks
+constexpr int FUSED_MIN_BLOCKS = 512;
+static void forward_infer(rsur_ctx* c, const float* X, int B, int Mp) {
+  const int dmax = *std::max_element(c->dp.begin(), c->dp.end());
+  if (dmax > FW || c->L > MAXL || (long long)(Mp / 64) * c->K < FUSED_MIN_BLOCKS) {
+    normalise_inputs(c, X, B, Mp);
+    forward_layers(c, Mp);
+    return;
+  }
+  if (c->pbt_stale) {
+    for (int l = 0; l < c->L; ++l) {
+      const long long n = (long long)c->dp[l] * c->dp[l + 1];
+      hipLaunchKernelGGL(k_transpose_w, dim3((unsigned)((n + 255) / 256), c->K), dim3(256), 0, c->stream, c->pb,
+                         c->pbt, c->P, c->woff[l], c->dp[l], c->dp[l + 1]);
+    }
+    c->pbt_stale = false;
+  }
+  MlpArgs g{};
+  g.X = X; g.B = B; g.din = c->din; g.xmu = c->xmu; g.xsd = c->xsd;
+  g.wt = c->pbt; g.sW = c->P; g.p = c->p; g.sP = c->P;
+  g.L = c->L;
+  for (int l = 0; l <= c->L; ++l) g.dp[l] = c->dp[l];
+  for (int l = 0; l < c->L; ++l) { g.woff[l] = c->woff[l]; g.boff[l] = c->boff[l]; }
+  g.out = c->out; g.sOut = (long long)c->Mp * c->dp[c->L]; g.ldo = c->dp[c->L];
+  hipLaunchKernelGGL(k_mlp_forward, dim3(Mp / 64, c->K), dim3(256), 0, c->stream, g);
+}
+
 static int forward_common(rsur_ctx* c, const void* X_dev, int32_t B, float* mean, float* var, float* members) {
   int e = check_batch(c, B);
   if (e) return e;
   const int Mp = pad64(B);
-  normalise_inputs(c, (const float*)X_dev, B, Mp);
-  forward_layers(c, Mp);
+  forward_infer(c, (const float*)X_dev, B, Mp);
   const long long n = (long long)B * c->dout;
   hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->out,
                      (long long)c->Mp * c->dp[c->L], c->dp[c->L], c->K, B, c->dout, c->ymu, c->ysd, mean, var, members);
@@ -335,6 +366,7 @@ int rsur_train_step(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t B
   const long long n = (long long)c->K * c->P;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->p, c->g, c->m1, c->m2,
                      c->pb, c->P, c->K, c->c1, c->c2, lr, 0.9f, 0.999f, 1e-8f);
+  c->pbt_stale = true;
   RCHK(c, hipGetLastError());
   if (loss) {
     RCHK(c, hipMemcpyAsync(loss, c->loss, sizeof(float) * c->K, hipMemcpyDeviceToHost, c->stream));

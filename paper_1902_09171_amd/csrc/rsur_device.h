@@ -97,6 +97,99 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
 }
 
+// ------------------------------------------------------------------ fused inference
+// Every layer of one member for 64 rows in one block: the activations stay in LDS (one buffer,
+// overwritten in place between two barriers per layer), the weights are read from L2 in a
+// transposed copy (WT[n][k], so a lane's 8 consecutive k are one 16-byte load) straight into the
+// matrix-core B operand, and the first layer normalises the raw inputs itself.  Wave w computes
+// output columns [64 w, 64 w + 64) of a layer as 2 x 2 tiles of v_mfma_f32_32x32x16_bf16 over k
+// in steps of 16 - the operand layout and k order of k_gemm, so the outputs equal the layer-wise
+// forward bit for bit.  Padded widths up to FW.
+constexpr int FW = 256, FLD = FW + 8, MAXL = 8;
+
+struct MlpArgs {
+  const float* X; int B, din;
+  const float *xmu, *xsd;
+  const bf16* wt; long long sW;              // transposed BF16 weights, member stride
+  const float* p; long long sP;              // FP32 parameters (biases), member stride
+  int L;
+  int dp[MAXL + 1];
+  long long woff[MAXL], boff[MAXL];
+  float* out; long long sOut; int ldo;       // K x Mp x dp[L]
+};
+
+__global__ __launch_bounds__(256, 2) void k_mlp_forward(MlpArgs g) {
+  __shared__ __attribute__((aligned(16))) bf16 act[64 * FLD];
+  const int mem = blockIdx.y;
+  const int m0 = blockIdx.x * 64;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int d0 = g.dp[0];
+  for (int e = t; e < 64 * d0; e += 256) {
+    const int r = e / d0, k = e % d0, m = m0 + r;
+    act[r * FLD + k] = (m < g.B && k < g.din) ? (bf16)((g.X[(long long)m * g.din + k] - g.xmu[k]) / g.xsd[k])
+                                              : (bf16)0.0f;
+  }
+  __syncthreads();
+  const bf16* Wm = g.wt + mem * g.sW;
+  const float* Pm = g.p + mem * g.sP;
+  const int ka = 8 * (l >> 5), ra = l & 31;
+  for (int L = 0; L < g.L; ++L) {
+    const int K = g.dp[L], N = g.dp[L + 1];
+    const int nc = 64 * w;
+    const bool on = nc < N;
+    v16f acc[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][c][r] = 0.0f;
+    if (on) {
+      const bf16* WT0 = Wm + g.woff[L] + (long long)(nc + ra) * K + ka;
+      const bf16* WT1 = WT0 + 32LL * K;
+#pragma unroll 2
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        const v8bf b0 = *(const v8bf*)(WT0 + k0);
+        const v8bf b1 = *(const v8bf*)(WT1 + k0);
+        const v8bf a0 = *(const v8bf*)&act[ra * FLD + k0 + ka];
+        const v8bf a1 = *(const v8bf*)&act[(32 + ra) * FLD + k0 + ka];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();                             // every wave has read this layer's input
+    if (on) {
+      const bool last = L == g.L - 1;
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int col = nc + 32 * c + (l & 31);
+          const float bias = Pm[g.boff[L] + col];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = 32 * q + (r >> 2) * 8 + (l >> 5) * 4 + (r & 3);
+            const float z = acc[q][c][r] + bias;
+            if (!last) act[row * FLD + col] = (bf16)silu(z);
+            else g.out[mem * g.sOut + (long long)(m0 + row) * g.ldo + col] = z;
+          }
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// transposed BF16 copy of one layer's weights for every member: WT[n][k] = W[k][n]
+__global__ void k_transpose_w(const bf16* pb, bf16* pbt, long long P, long long off, int Kd, int Nd) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int mem = blockIdx.y;
+  if (e >= (long long)Kd * Nd) return;
+  const int n = (int)(e / Kd), k = (int)(e % Kd);
+  pbt[mem * P + off + e] = pb[mem * P + off + (long long)k * Nd + n];
+}
+
 // raw inputs (B x din, FP32) -> normalised BF16 rows of width dp0, zero padding
 __global__ void k_norm_in(const float* X, int B, int din, int Mp, int dp0, const float* mu, const float* sd, bf16* out) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -125,3 +125,26 @@ def test_fit_norm_statistics(env):
     net.forward(X4.data_ptr(), 4, mean.data_ptr(), None)
     torch.cuda.synchronize()
     assert np.allclose(mean.cpu().numpy(), np.broadcast_to(Y.mean(0), (4, 2)), rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("B", [64, 200, 7000])
+def test_fused_inference_matches_the_training_forward(env, B):
+    # large batches run inference with all layers in one kernel, small ones layer by layer, and
+    # training always layer by layer.  Same operands and the same order of matrix-core products:
+    # the loss train_step reports (computed from its own forward, before the update) equals the
+    # loss of the inference outputs up to summation order (7000 rows x 5 members take the fused path)
+    torch, rsur = env
+    kw = dict(din=153, width=256, depth=4, dout=6)
+    net, params = make(rsur, kw, 5, seed=9, max_batch=8192)     # 7000 rows x 5 members run fused
+    X, Y = regression_data(B, 153, 6, seed=4)
+    x_mu, x_sd, y_mu, y_sd = X.mean(0), X.std(0) + 0.1, Y.mean(0), Y.std(0) + 0.1
+    net.set_norm(x_mu, x_sd, y_mu, y_sd)
+    Xd, Yd = dev(torch, X), dev(torch, Y)
+    out = torch.zeros((5, B, 6), dtype=torch.float32, device="cuda:0")
+    net.forward_members(Xd.data_ptr(), B, out.data_ptr())
+    torch.cuda.synchronize()
+    yn = (out.cpu().numpy().astype(np.float64) - y_mu) / y_sd
+    l_fused = ((yn - (Y - y_mu) / y_sd) ** 2).mean(axis=(1, 2))
+    loss = net.train_step(Xd.data_ptr(), Yd.data_ptr(), B, 1e-6)
+    print("fused", l_fused, "training forward", loss, flush=True)
+    assert np.allclose(loss, l_fused, rtol=2e-5)
