@@ -8,6 +8,8 @@ Workloads (``--workload``; every run prints one JSON line):
               steps run (neighbour builds, two-pass EAM forces fused with the Langevin
               velocity-Verlet update, per-cell stress reduction), and the window-averaged stress is
               rotated to the FE frame into device memory.
+  cu_batched  the same copper element batched 32 times (256 cells, 1.02 M atoms): the EAM kernels
+              with the GPU full.
   kg_single   one Kremer-Grest cell of 20 x 50 beads in FP64; F ramped to a 20 % uniaxial
               isochoric stretch over 1000 MD steps (a new F before every step), stress read every
               100 steps.  A step is one MD step; latency bound.
@@ -52,8 +54,8 @@ PAIRS_PER_ATOM = 67           # unique neighbours within 1.95 a in FCC copper
 # written (96 B), plus the two chain partners as 32-bit indices (8 B)
 BYTES_PER_BEAD_STEP = 104
 
-DEFAULTS = {"cu_element": (50, 3), "kg_single": (1000, 100), "kg_batched": (10, 1), "fe_bar": (4, 1),
-            "surrogate": (200, 20)}
+DEFAULTS = {"cu_element": (50, 3), "cu_batched": (10, 2), "kg_single": (1000, 100), "kg_batched": (10, 1),
+            "fe_bar": (4, 1), "surrogate": (200, 20)}
 
 
 def kernel_source_hash():
@@ -147,10 +149,10 @@ def check_status(g):
 
 
 # ------------------------------------------------------------------ workloads
-def bench_cu_element(args, torch, rcell, configs):
+def bench_cu_element(args, torch, rcell, configs, ncells=8):
     import numpy as np
     MD_PER_LOAD = 100
-    cfg = configs.cu_element()
+    cfg = configs.cu_element(ncells=ncells)
     ncells = len(cfg["cells"])
     natoms = sum(len(c["x"]) for c in cfg["cells"])
     dev = torch.device("cuda:0")
@@ -187,19 +189,27 @@ def bench_cu_element(args, torch, rcell, configs):
                 "frac": achieved / PEAK_FP32, "traffic": traffic_from_profiles("k_force_eam", "cu_element"),
                 "kernel": "k_force_eam", "avg_us": avg_s * 1e6, "launches": force_n,
                 "density_pass_avg_us": rho_s * 1e6, "flop_per_launch": flop_launch}
-    out = md_line(args, "cu_element", value, elapsed, natoms,
-                  {"description": "8 FCC copper r-cells x 4000 atoms (one hex8 element, 2x2x2 Gauss "
-                                  "points), Sutton-Chen EAM, 300 K, dt 1 fs, rotated uniaxial F ramp to 5 %, "
-                                  "100 MD steps per load step",
+    name = "cu_element" if ncells == 8 else "cu_batched"
+    what = ("8 FCC copper r-cells x 4000 atoms (one hex8 element, 2x2x2 Gauss points)" if ncells == 8 else
+            f"{ncells} FCC copper r-cells x 4000 atoms (the copper element batched {ncells // 8} times)")
+    out = md_line(args, name, value, elapsed, natoms,
+                  {"description": what + ", Sutton-Chen EAM, 300 K, dt 1 fs, rotated uniaxial F ramp to 5 %, "
+                                         "100 MD steps per load step",
                    "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
                    "lanes_per_atom": lanes}, roofline)
     if not args.no_cpu_baseline:
-        cb, s_ora = oracle_sample(cfg["params"], cfg["cells"], cfg["F_path"][0], args.cpu_sample_steps,
-                                  "first load step of the same element")
+        sub = list(range(8))
+        cells8, F8 = [cfg["cells"][c] for c in sub], cfg["F_path"][0][sub]
+        cb, s_ora = oracle_sample(cfg["params"], cells8, F8, args.cpu_sample_steps,
+                                  "first load step of the first 8 cells")
         out["cpu_baseline"] = cb
-        out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cfg["cells"], cfg["F_path"][0],
+        out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cells8, F8,
                                                            args.cpu_sample_steps, s_ora, lanes)
     return out
+
+
+def bench_cu_batched(args, torch, rcell, configs):
+    return bench_cu_element(args, torch, rcell, configs, ncells=256)
 
 
 def bench_kg_single(args, torch, rcell, configs):
@@ -455,7 +465,8 @@ def bench_surrogate(args, torch, rcell, configs):
     return out
 
 
-WORKLOADS = {"cu_element": bench_cu_element, "kg_single": bench_kg_single, "kg_batched": bench_kg_batched,
+WORKLOADS = {"cu_element": bench_cu_element, "cu_batched": bench_cu_batched, "kg_single": bench_kg_single,
+             "kg_batched": bench_kg_batched,
              "fe_bar": bench_fe_bar, "surrogate": bench_surrogate}
 
 

@@ -9,7 +9,8 @@
 //               per-component minimum image in scaled space: the pair separation needs no
 //               image shifts and no FP64 arithmetic (d = H dS, H as a float hi + lo pair).
 //   sb          s at the last neighbour build (displacement check)
-//   nbr         Verlet list within rc + skin, column-major nbr[k * npad + i], cell-local j
+//   nbr         Verlet list within rc + skin, column-major nbr[k * npad + i], cell-local j, as
+//               16-bit indices when every cell has at most 65536 atoms (mixed precision), else 32-bit
 //   bond        up to four FENE partners per atom (cell-local positions, -1 = none)
 //   gid         original cell-local index of the atom stored at each position; pos_of inverts it;
 //               bond0 holds the partners by original index.  At every neighbour build a cell's
@@ -84,7 +85,7 @@ struct MDArgs {
   int* pos_of;
   char* pscr;                      // reorder scratch: 6 doubles, one S and two ints per atom (npad rows)
   int* nn;
-  int* nbr;
+  void* nbr;                       // LT entries (uint16_t or int), see the kernels' LT parameter
   long long npad;
   int maxnb;
   CellDev* cells;
@@ -478,7 +479,7 @@ __device__ __forceinline__ void write_part(Part* parts, int part, const double W
 // entry (in bounds) and come back with ok = false, so the pair loops run straight-line code and
 // mask those slots out.  All UNR index loads, then all UNR gathers, are issued before any
 // arithmetic so that their latencies overlap.  sc points at the cell's first atom.
-template <class P, int TPA>
+template <class P, int TPA, class LT>
 __device__ __forceinline__ void gather_nbrs(const MDArgs& a, const typename P::S* sc, long long i, int nn, int k0,
                                             typename P::S sj[UNR], bool ok[UNR]) {
   int jj[UNR];
@@ -487,7 +488,7 @@ __device__ __forceinline__ void gather_nbrs(const MDArgs& a, const typename P::S
   for (int u = 0; u < UNR; ++u) {
     const int k = k0 + u * TPA;
     ok[u] = k < nn;
-    jj[u] = a.nbr[(unsigned)min(k, nn - 1) * np + ii];
+    jj[u] = (int)((const LT*)a.nbr)[(unsigned)min(k, nn - 1) * np + ii];
   }
 #pragma unroll
   for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, jj[u]);
@@ -495,7 +496,7 @@ __device__ __forceinline__ void gather_nbrs(const MDArgs& a, const typename P::S
 
 // Kremer-Grest: LJ truncated and shifted at rc on every listed pair + FENE on bonds; then the
 // integration tail.  TPA lanes share one atom's neighbour list.
-template <class P, int TPA>
+template <class P, int TPA, class LT>
 __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
       typename P::S sj[UNR];
       bool ok[UNR];
-      gather_nbrs<P, TPA>(a, sc, i, nn, k0, sj, ok);
+      gather_nbrs<P, TPA, LT>(a, sc, i, nn, k0, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         R d[3];
@@ -583,7 +584,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
 }
 
 // Sutton-Chen pass 1: host density rho_i and F'(rho_i) = -eps c / (2 sqrt(rho_i)), stored in s.w
-template <class P, int TPA, int SN, int SM>
+template <class P, int TPA, int SN, int SM, class LT>
 __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   using R = typename P::R;
   const int tb = block_tile(a.ntiles, blockIdx.x);
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
       typename P::S sj[UNR];
       bool ok[UNR];
-      gather_nbrs<P, TPA>(a, sc, i, nn, k0, sj, ok);
+      gather_nbrs<P, TPA, LT>(a, sc, i, nn, k0, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         R d[3];
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
 }
 
 // Sutton-Chen pass 2: pair scalar g = eps phi'(r) + (F'_i + F'_j) rho'(r), then the tail
-template <class P, int TPA, int SN, int SM>
+template <class P, int TPA, int SN, int SM, class LT>
 __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
@@ -648,7 +649,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
       typename P::S sj[UNR];
       bool ok[UNR];
-      gather_nbrs<P, TPA>(a, sc, i, nn, k0, sj, ok);
+      gather_nbrs<P, TPA, LT>(a, sc, i, nn, k0, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         R d[3];
@@ -1044,7 +1045,7 @@ __global__ __launch_bounds__(TILE) void k_reset_order(MDArgs a, int first, int c
 constexpr int LPA = 8;
 constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
 constexpr int STASH = 8;
-template <class P>
+template <class P, class LT>
 __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
   constexpr int PER_TILE = TILE / BUILD_ATOMS;
   constexpr int NT = BUILD_ATOMS * LPA;
@@ -1129,11 +1130,11 @@ __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
   const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
   if (!over) {
     for (int e = 0; e < mine; ++e)
-      if (base + e < a.maxnb) a.nbr[(unsigned)(base + e) * np + ii] = stash[e * NT + threadIdx.x];
+      if (base + e < a.maxnb) ((LT*)a.nbr)[(unsigned)(base + e) * np + ii] = (LT)stash[e * NT + threadIdx.x];
   } else {
     int k = base;
     scan_bins([&](int lj) {
-      if (k < a.maxnb) a.nbr[(unsigned)k * np + ii] = lj;
+      if (k < a.maxnb) ((LT*)a.nbr)[(unsigned)k * np + ii] = (LT)lj;
       ++k;
     });
   }

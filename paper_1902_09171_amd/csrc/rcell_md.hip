@@ -45,7 +45,9 @@ struct rcell_ctx {
   int4 *bond = nullptr, *bond0 = nullptr;
   int *gid = nullptr, *pos_of = nullptr;
   char* pscr = nullptr;           // reorder scratch rows
-  int *nn = nullptr, *nbr = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr, *sort_tmp = nullptr;
+  void* nbr = nullptr;
+  bool list16 = false;            // 16-bit list entries (every cell has at most 65536 atoms, mixed)
+  int *nn = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr, *sort_tmp = nullptr;
   int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
   CellDev* cells = nullptr;
   Tile* tiles = nullptr;
@@ -235,44 +237,46 @@ struct ProfScope {
   }
 };
 
-template <class P, int TPA, int SN, int SM>
+template <class P, int TPA, int SN, int SM, class LT>
 void force_eam_t(rcell_ctx* c, const MDArgs& a, int mode) {
   const dim3 grid(tile_grid(c->ntiles)), block(TILE * TPA);
   {
     ProfScope ps(c, 1);
-    hipLaunchKernelGGL((k_eam_rho<P, TPA, SN, SM>), grid, block, 0, c->stream, a, mode);
+    hipLaunchKernelGGL((k_eam_rho<P, TPA, SN, SM, LT>), grid, block, 0, c->stream, a, mode);
   }
   ProfScope ps(c, 0);
-  hipLaunchKernelGGL((k_force_eam<P, TPA, SN, SM>), grid, block, 0, c->stream, a, mode);
+  hipLaunchKernelGGL((k_force_eam<P, TPA, SN, SM, LT>), grid, block, 0, c->stream, a, mode);
 }
 
-template <class P, int TPA>
+template <class P, int TPA, class LT>
 void force_t(rcell_ctx* c, const MDArgs& a, int mode) {
   if (c->p.potential == RCELL_POT_KG) {
     ProfScope ps(c, 0);
-    hipLaunchKernelGGL((k_force_kg<P, TPA>), dim3(tile_grid(c->ntiles)), dim3(TILE * TPA), 0, c->stream, a, mode);
+    hipLaunchKernelGGL((k_force_kg<P, TPA, LT>), dim3(tile_grid(c->ntiles)), dim3(TILE * TPA), 0, c->stream, a, mode);
   } else if (a.sc_n == 9 && a.sc_m == 6) {      // copper, nickel: exponents fixed at compile time
-    force_eam_t<P, TPA, 9, 6>(c, a, mode);
+    force_eam_t<P, TPA, 9, 6, LT>(c, a, mode);
   } else {
-    force_eam_t<P, TPA, 0, 0>(c, a, mode);
+    force_eam_t<P, TPA, 0, 0, LT>(c, a, mode);
   }
 }
 
-template <class P>
+template <class P, class LT>
 void force_p(rcell_ctx* c, const MDArgs& a, int mode, int lanes) {
   switch (lanes) {
-    case 2: force_t<P, 2>(c, a, mode); break;
-    case 4: force_t<P, 4>(c, a, mode); break;
-    case 8: force_t<P, 8>(c, a, mode); break;
-    case 16: force_t<P, 16>(c, a, mode); break;
-    default: force_t<P, 1>(c, a, mode); break;
+    case 2: force_t<P, 2, LT>(c, a, mode); break;
+    case 4: force_t<P, 4, LT>(c, a, mode); break;
+    case 8: force_t<P, 8, LT>(c, a, mode); break;
+    case 16: force_t<P, 16, LT>(c, a, mode); break;
+    default: force_t<P, 1, LT>(c, a, mode); break;
   }
 }
 
 void launch_force(rcell_ctx* c, int mode, int lanes = -1) {
   const MDArgs a = make_args(c);
   const int l = lanes > 0 ? lanes : c->lanes;
-  if (c->fp64) force_p<FP64>(c, a, mode, l); else force_p<Mixed>(c, a, mode, l);
+  if (c->fp64) force_p<FP64, int>(c, a, mode, l);
+  else if (c->list16) force_p<Mixed, uint16_t>(c, a, mode, l);
+  else force_p<Mixed, int>(c, a, mode, l);
 }
 
 void launch_reduce(rcell_ctx* c, int mode) {
@@ -297,8 +301,9 @@ void launch_build(rcell_ctx* c) {
     hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gt, bt, 0, c->stream, a);
   }
   const dim3 gl(tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)), bl(BUILD_ATOMS * LPA);
-  if (c->fp64) hipLaunchKernelGGL(k_build_list<FP64>, gl, bl, 0, c->stream, a);
-  else hipLaunchKernelGGL(k_build_list<Mixed>, gl, bl, 0, c->stream, a);
+  if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a);
+  else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a);
+  else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a);
 }
 
 void launch_start(rcell_ctx* c) {
@@ -409,7 +414,9 @@ int ensure_list_capacity(rcell_ctx* c, int need) {
   drop_graphs(c);
   dfree(c, c->nbr);
   c->nbr = nullptr;
-  const int st = dalloc(c, &c->nbr, (size_t)need * c->npad);
+  char* q = nullptr;
+  const int st = dalloc(c, &q, (size_t)need * c->npad * (c->list16 ? sizeof(uint16_t) : sizeof(int)));
+  c->nbr = q;
   if (st) return st;
   c->maxnb = need;
   return RCELL_OK;
@@ -525,6 +532,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
   if (N > (1ll << 31) - 1) return bail(fail(c, RCELL_ERR_ARG, "too many atoms"));
   c->N = N;
   c->npad = (N + 63) / 64 * 64;
+  c->list16 = !c->fp64 && *std::max_element(c->n.begin(), c->n.end()) <= 65536;
   c->ntiles = ntiles;
   c->occ.assign(ncells, 0.0);
   for (int k = 0; k < ncells; ++k) set_occupancy(c, k, (double)cells[k].natoms / bins_exact(cells[k].H0, rcs));
