@@ -71,6 +71,7 @@ def lib():
             "orc_create": [vp, i32, vp, vp, vp, vp, vp, vp, vp],
             "orc_set_deformation": [vp, vp], "orc_run": [vp, i32], "orc_get_stress": [vp, vp, vp],
             "orc_set_cell_ids": [vp, vp],
+            "orc_minimize": [vp, i32, ctypes.c_double, vp],
             "orc_get_status": [vp, vp], "orc_get_forces": [vp, i32, vp],
             "orc_get_state": [vp, i32, vp, vp, vp, vp, vp],
             "orc_set_state": [vp, i32, vp, vp, vp, vp, i64], "orc_get_energy": [vp, vp, vp],
@@ -212,6 +213,12 @@ class OracleBatch:
 
     def run(self, nsteps):
         self._check(lib().orc_run(self._h, int(nsteps)), "run")
+
+    def minimize(self, max_iter, ftol):
+        """Molecular statics by FIRE (see orc_minimize); returns the iterations used per cell."""
+        iters = np.zeros(self.ncells, np.int32)
+        self._check(lib().orc_minimize(self._h, int(max_iter), float(ftol), _p(iters)), "minimize")
+        return iters
 
     def get_stress(self, with_P=False):
         s = np.zeros((self.ncells, 6))

@@ -547,6 +547,69 @@ int orc_run(orc_ctx* C, int32_t nsteps) {
   return st_all;
 }
 
+/* Molecular statics (Sec. 2.1, Eqs. 16-20): relax each cell's atoms in its current box to a minimum
+ * of the potential energy, starting from the current positions - after a deformation these are the
+ * affine guess F H(0) S(t-1) of Eq. 17 - and return the stress of the relaxed configuration
+ * (Eq. 20 is J sigma F^-T of its virial stress, which get_stress returns).  The minimiser is FIRE
+ * (Bitzek, Koskinen, Gaehler, Moseler, Gumbsch, Phys. Rev. Lett. 97, 170201 (2006)): per iteration,
+ * forces at the current positions; stop when max_i |f_i| <= ftol; if the power P = f.v is positive,
+ * the velocity is mixed towards the force, v = (1 - alpha) v + alpha |v| f / |f| (norms over the
+ * cell), and after more than 5 such iterations in a row dt grows by 1.1 (at most 10 MD time steps)
+ * and alpha shrinks by 0.99; otherwise dt halves, alpha returns to 0.1 and v is zeroed; then
+ * v += dt f / m and x += dt v.  dt starts at the MD time step.  Afterwards v = 0, f holds the
+ * conservative force, the stress window is empty and its last sample is the relaxed stress. */
+int orc_minimize(orc_ctx* C, int32_t max_iter, double ftol, int32_t* iters) {
+  if (!C || max_iter < 0 || !(ftol > 0)) return E_ARG;
+  int st_all = OK;
+#pragma omp parallel for schedule(dynamic) reduction(min : st_all)
+  for (int32_t k = 0; k < C->ncells; ++k) {
+    ocell* c = &C->c[k];
+    const orc_params* p = &C->p;
+    const int64_t n3 = 3 * (int64_t)c->n;
+    const double inv_m = 1.0 / (p->mass * p->mvv2e), dt_max = 10.0 * p->dt;
+    double dt = p->dt, alpha = 0.1, W[9];
+    int32_t count = 0, it = 0;
+    int st = OK;
+    memset(c->v, 0, (size_t)n3 * sizeof(double));
+    for (;;) {
+      wrap_positions(c);
+      st = eval_forces(p, c->H, c->n, c->x, c->nb, c->bonds, c->f, &c->pe, W, &c->L);
+      if (st != OK) break;
+      double fmax2 = 0.0, P = 0.0, F2 = 0.0, V2 = 0.0;
+      for (int32_t i = 0; i < c->n; ++i) {
+        const double* f = &c->f[3 * i];
+        const double* v = &c->v[3 * i];
+        const double f2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];
+        fmax2 = fmax(fmax2, f2);
+        F2 += f2;
+        V2 += v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        P += f[0] * v[0] + f[1] * v[1] + f[2] * v[2];
+      }
+      if (fmax2 <= ftol * ftol || it >= max_iter) break;
+      if (P > 0.0) {
+        if (++count > 5) { dt = fmin(1.1 * dt, dt_max); alpha *= 0.99; }
+        const double a = 1.0 - alpha, b = alpha * sqrt(V2 / F2);
+        for (int64_t q = 0; q < n3; ++q) c->v[q] = a * c->v[q] + b * c->f[q];
+      } else {
+        dt *= 0.5;
+        alpha = 0.1;
+        count = 0;
+        memset(c->v, 0, (size_t)n3 * sizeof(double));
+      }
+      for (int64_t q = 0; q < n3; ++q) c->v[q] += dt * inv_m * c->f[q];
+      for (int64_t q = 0; q < n3; ++q) c->x[q] += dt * c->v[q];
+      ++it;
+    }
+    memset(c->v, 0, (size_t)n3 * sizeof(double));
+    if (st == OK) sample_stress(p, c, W, c->last);
+    for (int q = 0; q < 6; ++q) c->wsum[q] = 0.0;
+    c->wcount = 0;
+    if (iters) iters[k] = it;
+    if (st != OK) { c->status = st; st_all = st; }
+  }
+  return st_all;
+}
+
 /* sigma_FEM = Q sigma_MD Q^T (Eq. 7) and P = J sigma_FEM F^-T (Eq. 8); Voigt in and out. */
 static void stress_return(const double Q[9], const double F[9], double J, const double sv[6],
                           double out6[6], double* P9) {

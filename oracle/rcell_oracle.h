@@ -44,6 +44,7 @@ int  orc_create(const orc_params* p, int32_t ncells, const int32_t* natoms, cons
 int  orc_set_deformation(orc_ctx* c, const double* F);
 int  orc_set_cell_ids(orc_ctx* c, const int32_t* ids);   /* noise-counter index of each cell */
 int  orc_run(orc_ctx* c, int32_t nsteps);
+int  orc_minimize(orc_ctx* c, int32_t max_iter, double ftol, int32_t* iters);   /* statics, FIRE */
 int  orc_get_stress(orc_ctx* c, double* sigma, double* P);
 int  orc_get_status(orc_ctx* c, int32_t* status);
 int  orc_get_forces(orc_ctx* c, int32_t cell, double* f);

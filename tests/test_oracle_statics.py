@@ -1,0 +1,97 @@
+"""Pins of the oracle's molecular statics (Sec. 2.1, Eqs. 16-20; FIRE minimiser).
+
+A monatomic Bravais lattice has no internal relaxation: under a homogeneous F its energy minimum is
+the affinely deformed perfect lattice (the Cauchy-Born configuration).  So a perturbed copper cell
+relaxed in the deformed box must return to the Cauchy-Born energy, and its relaxed first
+Piola-Kirchhoff stress must be (1/Omega_0) dE_CB/dF, checked here by central differences of the
+energy of the deformed perfect lattice - which pins the virial of Eq. 15, the stress return of
+Eqs. 7-8 and Eq. 20 together.  Rotating F rotates the relaxed Cauchy stress (frame indifference)."""
+import numpy as np
+import pytest
+
+from oracle import core
+from synth import configs, fcc_lattice, random_rotation
+from synth.rng import generator
+
+P_CU = configs.cu_params(precision="fp64", skin=0.5, gamma=0.0, temperature=0.0)
+F_GEN = np.array([[1.02, 0.01, 0.0], [0.0, 0.99, 0.015], [0.0, 0.0, 1.005]])
+
+
+def cu_perturbed(seed, ncell=6, amp=0.05):
+    x, H = fcc_lattice(ncell)
+    rng = np.random.default_rng(seed)
+    return dict(x=x + rng.normal(0.0, amp, x.shape), v=np.zeros_like(x), bonds=np.zeros((0, 2), np.int32), H0=H), x, H
+
+
+def cb_energy(F, x, H0):
+    """Energy of the perfect lattice deformed affinely by F (box F H0)."""
+    _, pe, _ = core.forces(P_CU, F @ H0, x @ F.T)
+    return pe
+
+
+def test_relaxes_to_the_cauchy_born_lattice():
+    cell, x0, H0 = cu_perturbed(1)
+    o = core.OracleBatch(P_CU, [cell])
+    o.set_deformation(F_GEN[None])
+    it = o.minimize(5000, 1e-7)
+    pe, ke = o.get_energy()
+    e_cb = cb_energy(F_GEN, x0, H0)
+    n = len(x0)
+    print("iterations", it, "E - E_CB per atom", (pe[0] - e_cb) / n, flush=True)
+    assert it[0] < 5000 and ke[0] == 0.0
+    assert abs(pe[0] - e_cb) / n < 1e-10
+    assert np.abs(o.get_forces(0)).max() <= 1e-7 * np.sqrt(3)
+
+
+def test_relaxed_stress_is_the_energy_derivative():
+    cell, x0, H0 = cu_perturbed(2)
+    o = core.OracleBatch(P_CU, [cell])
+    o.set_deformation(F_GEN[None])
+    o.minimize(5000, 1e-7)
+    _, P = o.get_stress(with_P=True)
+    omega0 = np.linalg.det(H0)
+    h = 1e-5
+    P_fd = np.zeros((3, 3))
+    for a in range(3):
+        for b in range(3):
+            dF = np.zeros((3, 3))
+            dF[a, b] = h
+            P_fd[a, b] = (cb_energy(F_GEN + dF, x0, H0) - cb_energy(F_GEN - dF, x0, H0)) / (2 * h * omega0)
+    print("P", P[0], "P_fd", P_fd, flush=True)
+    assert np.abs(P[0] - P_fd).max() <= 1e-6 * np.abs(P_fd).max()
+
+
+def test_statics_is_frame_indifferent():
+    cell, _, _ = cu_perturbed(3)
+    Q = random_rotation(generator(11, 0))
+    s = []
+    for F in (F_GEN, Q @ F_GEN):
+        o = core.OracleBatch(P_CU, [cell])
+        o.set_deformation(F[None])
+        o.minimize(5000, 1e-7)
+        s.append(o.get_stress()[0])
+
+    def full(v):
+        return np.array([[v[0], v[3], v[4]], [v[3], v[1], v[5]], [v[4], v[5], v[2]]])
+    rotated = Q @ full(s[0]) @ Q.T
+    assert np.abs(full(s[1]) - rotated).max() <= 1e-8 * np.abs(rotated).max()
+
+
+def test_polymer_cell_relaxes():
+    p = configs.kg_params(precision="fp64")
+    cell = configs.kg_cell([10] * 10, 77)
+    o = core.OracleBatch(p, [cell])
+    pe0 = o.get_energy()[0][0]
+    it = o.minimize(20000, 1e-2)
+    pe1 = o.get_energy()[0][0]
+    print("iterations", it, "energy", pe0, "->", pe1, flush=True)
+    assert it[0] < 20000 and pe1 < pe0
+    assert np.abs(o.get_forces(0)).max() <= 1e-2 * np.sqrt(3)
+
+
+@pytest.mark.parametrize("bad", [(-1, 1e-6), (10, 0.0)])
+def test_minimize_rejects_bad_arguments(bad):
+    cell, _, _ = cu_perturbed(4)
+    o = core.OracleBatch(P_CU, [cell])
+    with pytest.raises(core.OracleError):
+        o.minimize(*bad)
