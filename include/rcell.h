@@ -102,6 +102,18 @@ int rcell_set_deformation_dev(rcell_ctx* ctx, const void* F_dev);
  * capacity) set the cell's status and are returned by the next synchronising call. */
 int rcell_run(rcell_ctx* ctx, int32_t nsteps);
 
+/* Molecular statics (Sec. 2.1, Eqs. 16-20): relax every cell's atoms in its current box to a
+ * minimum of the potential energy, starting from the current positions - after a deformation these
+ * are the affine (Cauchy-Born) guess F H(0) S(t-1) of Eq. 17 - so that the next get_stress returns
+ * the 0 K stress of the relaxed configuration (Eq. 20 equals J sigma F^-T of its virial stress).
+ * Minimiser: FIRE (Bitzek et al., Phys. Rev. Lett. 97, 170201 (2006)); per cell, iterations until
+ * max_i |f_i| <= ftol (force units) or max_iter moves.  Afterwards velocities are zero, the stored
+ * force is the conservative one, the averaging window is empty and holds the relaxed stress as its
+ * last sample, and the MD step counter is unchanged (a later rcell_run continues MD from here).
+ * iters: ncells host int32 receiving the moves each cell used (or NULL).  Synchronises; returns
+ * RCELL_ERR_ARG for max_iter < 0 or ftol <= 0, else the first per-cell error status. */
+int rcell_minimize(rcell_ctx* ctx, int32_t max_iter, double ftol, int32_t* iters);
+
 /* Window average of sigma_MD since the last get_stress / set_deformation (or the instantaneous
  * stress if the window is empty), rotated to the FE frame sigma_FEM = Q sigma Q^T (Eq. 7), and
  * the first Piola-Kirchhoff stress P = J sigma_FEM F^-T (Eq. 8).  sigma: ncells*6 host doubles;

@@ -31,8 +31,8 @@ constexpr int UNR = 4;           // neighbour-loop unroll: gathers in flight per
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWOM32 = 1.0 / 4294967296.0;
 
-enum Mode : int { MODE_PRIME = 0, MODE_STEP = 1, MODE_LAST = 2, MODE_DRY = 3 };
-enum RedMode : int { RED_START = 0, RED_PRIME = 1, RED_STEP = 2, RED_LAST = 3 };
+enum Mode : int { MODE_PRIME = 0, MODE_STEP = 1, MODE_LAST = 2, MODE_DRY = 3, MODE_STATIC = 4 };
+enum RedMode : int { RED_START = 0, RED_PRIME = 1, RED_STEP = 2, RED_LAST = 3, RED_STATIC = 4, RED_MOVE = 5 };
 enum Status : int { ST_OK = 0, ST_BOND = -4, ST_CAP = -8, ST_BOX = -3, ST_BAD_F = -2 };
 
 struct alignas(32) S64 { long long x, y, z, w; };
@@ -53,6 +53,11 @@ struct CellDev {
   double Hb[6];                   // H at the last neighbour build, upper triangle (0 1 2 4 5 8)
   float hs2;                      // squared displacement that still keeps the list complete
   int pad2;
+  // molecular statics (FIRE): time step, mixing parameter, the velocity update of this iteration
+  // (v = fa v + fb f, or zero when frozen), iterations since the power last turned negative,
+  // converged flag and iterations used
+  double fdt, falpha, fa, fb;
+  int fcount, fdone, ffreeze, fiter;
 };
 
 struct Tile { int cell, begin, count, pad; };
@@ -96,6 +101,8 @@ struct MDArgs {
   long long bins_total;
   // integrator constants (computed once on the host, documented expressions)
   double dt, h, drag, c24, mmv, half_skin2, rcs2;
+  double fire_ftol2;               // statics: converged when max_i |f_i|^2 <= fire_ftol2
+  int fire_max_iter;               // statics: at most this many moves per cell
   uint32_t key0, key1;
   int gamma_on, include_kinetic, pot;
   // pair constants
@@ -356,6 +363,18 @@ __device__ __forceinline__ void atom_tail(const MDArgs& a, const CellDev& C, int
   double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
   const int gid = a.gid[i];
   double f0 = fcx, f1 = fcy, f2 = fcz;
+  if (mode == MODE_STATIC) {
+    // statics: keep the conservative force and report f.v, |f|^2, |v|^2 and max |f|^2 (FIRE)
+    ((typename P::Fst*)a.fx)[i] = (typename P::Fst)f0;
+    ((typename P::Fst*)a.fy)[i] = (typename P::Fst)f1;
+    ((typename P::Fst*)a.fz)[i] = (typename P::Fst)f2;
+    const double ff = f0 * f0 + f1 * f1 + f2 * f2;
+    o.K[0] = f0 * vx + f1 * vy + f2 * vz; o.K[1] = ff; o.K[2] = vx * vx + vy * vy + vz * vz;
+    o.K[3] = o.K[4] = o.K[5] = 0.0;
+    o.maxd2 = (float)ff;
+    o.xi[0] = o.xi[1] = o.xi[2] = 0;
+    return;
+  }
   if (mode == MODE_PRIME) {
     // forces after create / deformation / restore: conservative part only; v is a full-step velocity
     ((typename P::Fst*)a.fx)[i] = (typename P::Fst)f0;
@@ -506,7 +525,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
-  const bool skip = (mode == MODE_PRIME && !C.pending);
+  const bool skip = (mode == MODE_PRIME && !C.pending) || (mode == MODE_STATIC && C.fdone);
   const bool active = slot < t.count && !skip;
   const long long i = (long long)t.begin + slot;
   R f[3] = {0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
@@ -592,7 +611,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
-  const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending);
+  const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending) && !(mode == MODE_STATIC && C.fdone);
   const long long i = (long long)t.begin + slot;
   R rho = 0;
   if (active) {
@@ -634,7 +653,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
-  const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending);
+  const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending) && !(mode == MODE_STATIC && C.fdone);
   const long long i = (long long)t.begin + slot;
   R f[3] = {0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
   R fpi = 0;
@@ -730,12 +749,78 @@ __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
   write_part<TILE>(a.parts, tb, Z, Z, 0.0, xi, maxd2, 0, psh);
 }
 
+// ------------------------------------------------------------------ molecular statics (FIRE)
+// Start of a relaxation: FIRE state of every cell, empty stress window, zero velocities.
+__global__ void k_fire_cells(CellDev* cells, int ncells, double dt) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  CellDev& C = cells[c];
+  C.fdt = dt; C.falpha = 0.1; C.fa = 1.0; C.fb = 0.0;
+  C.fcount = 0; C.fdone = 0; C.ffreeze = 1; C.fiter = 0;
+  for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
+  C.wcount = 0;
+}
+
+__global__ __launch_bounds__(TILE) void k_zero_v(MDArgs a) {
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  if ((int)threadIdx.x >= t.count) return;
+  const long long i = (long long)t.begin + threadIdx.x;
+  a.vx[i] = 0.0; a.vy[i] = 0.0; a.vz[i] = 0.0;
+}
+
+// One FIRE move of the atoms of unconverged cells: velocity mixing (or zero), v += dt f / m,
+// x += dt v, new fixed-point coordinates and the displacement since the last build.
+template <class P>
+__global__ __launch_bounds__(TILE) void k_fire_move(MDArgs a) {
+  __shared__ PartShared<1> psh;
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  const CellDev& C = a.cells[t.cell];
+  const long long i = (long long)t.begin + threadIdx.x;
+  float maxd2 = 0.f;
+  if ((int)threadIdx.x < t.count && !C.fdone) {
+    const double f0 = (double)((const typename P::Fst*)a.fx)[i];
+    const double f1 = (double)((const typename P::Fst*)a.fy)[i];
+    const double f2 = (double)((const typename P::Fst*)a.fz)[i];
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (!C.ffreeze) {
+      vx = C.fa * a.vx[i] + C.fb * f0;
+      vy = C.fa * a.vy[i] + C.fb * f1;
+      vz = C.fa * a.vz[i] + C.fb * f2;
+    }
+    const double k = C.fdt * (2.0 * a.h / a.dt);    // dt / (m mvv2e)
+    vx += k * f0; vy += k * f1; vz += k * f2;
+    const double x = a.x[i] + C.fdt * vx, y = a.y[i] + C.fdt * vy, z = a.z[i] + C.fdt * vz;
+    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+    a.x[i] = x; a.y[i] = y; a.z[i] = z;
+    const typename P::S sn = fixed_pos<P>(C, x, y, z);
+    P::store_xyz(a.s_cur, i, sn);
+    typename P::R d[3];
+    P::sep(sn, P::load(a.sb, i), C, d);
+    maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  }
+  const double Z[6] = {0, 0, 0, 0, 0, 0};
+  const long long xi[3] = {0, 0, 0};
+  write_part<TILE>(a.parts, tb, Z, Z, 0.0, xi, maxd2, 0, psh);
+}
+
+__global__ void k_fire_iters(const CellDev* cells, int ncells, int* iters, int* done) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  iters[c] = cells[c].fiter;
+  done[c] = cells[c].fdone;
+}
+
 // Per-cell reduction of the tile partials: one wave per cell, each lane sums every 64th tile
 // in order, then a fixed xor-shuffle tree (deterministic for a given tile count).
 constexpr int RED_NT = 64;
 __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   CellDev& C = a.cells[blockIdx.x];
   if (mode == RED_PRIME && !C.pending) return;
+  if ((mode == RED_STATIC || mode == RED_MOVE) && C.fdone) return;
   double W[6] = {0, 0, 0, 0, 0, 0}, K[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
   long long xi[3] = {0, 0, 0};
   float m = 0.f;
@@ -758,6 +843,28 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   st = wave_min(st);
   if (threadIdx.x != 0) return;
   if (st != 0 && C.status == 0) C.status = st;
+  if (mode == RED_MOVE) {                // statics: positions moved; rebuild when they left the skin
+    C.rebuild = md > C.hs2;
+    return;
+  }
+  if (mode == RED_STATIC) {              // statics: one FIRE decision per cell (same order as the oracle)
+    C.pe = r[12];
+    const double P = r[6], F2 = r[7], V2 = r[8];
+    if ((double)md <= a.fire_ftol2 || st != 0 || C.fiter >= a.fire_max_iter) { C.fdone = 1; return; }
+    if (P > 0.0) {
+      if (++C.fcount > 5) { C.fdt = fmin(1.1 * C.fdt, 10.0 * a.dt); C.falpha *= 0.99; }
+      C.fa = 1.0 - C.falpha;
+      C.fb = C.falpha * sqrt(V2 / F2);
+      C.ffreeze = 0;
+    } else {
+      C.fdt *= 0.5;
+      C.falpha = 0.1;
+      C.fcount = 0;
+      C.ffreeze = 1;
+    }
+    C.fiter += 1;
+    return;
+  }
   if (C.rebuild) C.nrebuild += 1;
   if (mode == RED_START) {
     C.rebuild = md > C.hs2;

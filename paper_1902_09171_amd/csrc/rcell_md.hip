@@ -37,6 +37,8 @@ struct rcell_ctx {
   std::vector<int> off, n, tile_off, ntile, bin_off, bin_cap;
   long long bins_total = 0, bins_alloc = 0;
   std::vector<double> occ;        // expected atoms per bin of each cell
+  double fire_ftol2 = 0.0;        // statics: convergence threshold and move limit of the current call
+  int fire_max_iter = 0;
   int sort_cap = 256;             // keys staged in LDS per wave by the bin sort
   // device memory
   double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
@@ -181,6 +183,8 @@ MDArgs make_args(const rcell_ctx* c) {
   const rcell_params& p = c->p;
   // integrator constants: the same expressions, in the same order, as the method's definition
   a.dt = p.dt;
+  a.fire_ftol2 = c->fire_ftol2;
+  a.fire_max_iter = c->fire_max_iter;
   a.h = p.dt / (2.0 * p.mass * p.mvv2e);
   a.drag = -(p.gamma * p.mass * p.mvv2e);
   a.c24 = std::sqrt(24.0 * p.gamma * p.mass * p.kB * p.temperature * p.mvv2e / p.dt) * 0x1.0p-24;
@@ -741,6 +745,47 @@ int rcell_destroy(rcell_ctx* c) {
 }
 
 const char* rcell_last_error(const rcell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int rcell_minimize(rcell_ctx* c, int32_t max_iter, double ftol, int32_t* iters) {
+  if (!c) return RCELL_ERR_ARG;
+  if (max_iter < 0 || !(ftol > 0) || !std::isfinite(ftol)) return fail(c, RCELL_ERR_ARG, "max_iter >= 0 and ftol > 0");
+  const int nc = c->ncells;
+  c->fire_ftol2 = ftol * ftol;
+  c->fire_max_iter = max_iter;
+  const MDArgs a0 = make_args(c);
+  hipLaunchKernelGGL(k_fire_cells, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, nc, c->p.dt);
+  hipLaunchKernelGGL(k_zero_v, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a0);
+  int* d_it = c->iscratch;
+  int* d_done = c->iscratch + nc;
+  std::vector<int> done(nc);
+  for (long long it = 0; it <= max_iter; ++it) {
+    launch_force(c, MODE_STATIC);
+    launch_reduce(c, RED_STATIC);
+    const MDArgs a = make_args(c);
+    if (c->fp64) hipLaunchKernelGGL(k_fire_move<FP64>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_fire_move<Mixed>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a);
+    launch_reduce(c, RED_MOVE);
+    launch_build(c);
+    if (it % 16 == 15 || it == max_iter) {
+      hipLaunchKernelGGL(k_fire_iters, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, nc, d_it, d_done);
+      HIPCHK(c, hipMemcpyAsync(done.data(), d_done, sizeof(int) * nc, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (std::all_of(done.begin(), done.end(), [](int d) { return d != 0; })) break;
+    }
+  }
+  // relaxed state: zero velocities, conservative forces and the relaxed stress as the last sample
+  hipLaunchKernelGGL(k_zero_v, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a0);
+  hipLaunchKernelGGL(k_set_pending, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, nc);
+  int e = prime(c);
+  if (e) return e;
+  hipLaunchKernelGGL(k_fire_iters, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, nc, d_it, d_done);
+  std::vector<int> hit(nc);
+  HIPCHK(c, hipMemcpyAsync(hit.data(), d_it, sizeof(int) * nc, hipMemcpyDeviceToHost, c->stream));
+  Gathered g;
+  if ((e = gather(c, g))) return e;
+  if (iters) std::copy(hit.begin(), hit.end(), iters);
+  return first_error(c, g.status);
+}
 
 int rcell_get_status(rcell_ctx* c, int32_t* status) {
   if (!c || !status) return c ? fail(c, RCELL_ERR_ARG, "status is NULL") : RCELL_ERR_ARG;

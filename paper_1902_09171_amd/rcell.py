@@ -24,7 +24,7 @@ EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev",
            "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
            "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
            "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps",
-           "rcell_qr_dev", "rcell_stress_return_dev"]
+           "rcell_qr_dev", "rcell_stress_return_dev", "rcell_minimize"]
 
 
 class RCellError(RuntimeError):
@@ -68,6 +68,7 @@ def load():
         sig = {
             "rcell_create": [vp, vp, i32, vp, vp], "rcell_set_deformation": [vp, vp],
             "rcell_set_deformation_dev": [vp, vp], "rcell_run": [vp, i32],
+            "rcell_minimize": [vp, i32, ctypes.c_double, vp],
             "rcell_get_stress": [vp, vp, vp], "rcell_get_stress_dev": [vp, vp, vp],
             "rcell_get_stress_ext": [vp, vp, vp, vp],
             "rcell_destroy": [vp], "rcell_last_error": [vp], "rcell_get_status": [vp, vp],
@@ -178,6 +179,12 @@ class RCellBatch:
 
     def run(self, nsteps):
         self._check(load().rcell_run(self._h, int(nsteps)))
+
+    def minimize(self, max_iter, ftol):
+        """Molecular statics (FIRE relaxation in the current boxes); returns the moves per cell."""
+        iters = np.zeros(self.ncells, np.int32)
+        self._check(load().rcell_minimize(self._h, int(max_iter), float(ftol), iters.ctypes.data))
+        return iters
 
     def get_stress(self, with_P=False):
         s = np.zeros((self.ncells, 6))

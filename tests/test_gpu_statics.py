@@ -1,0 +1,112 @@
+"""Molecular statics on the GPU (rcell_minimize: FIRE relaxation in the deformed box, Eqs. 16-20)
+against the FP64 oracle.
+
+Copper cells: the relaxed energy per atom, stress and P match the oracle's at the mixed-precision
+tolerance; where the affinely deformed lattice is stable (a monatomic Bravais lattice has no
+internal relaxation) the relaxed energy is the Cauchy-Born value - Table 1's C(t) is beyond the
+crystal's stability, and both sides relax it to the same lower state.  A polymer cell in FP64 mode: its relaxed
+configuration is a minimum by the oracle's own force evaluation.  Edge cases: max_iter = 0, bad
+arguments, and MD continuing from a relaxed state."""
+import numpy as np
+import pytest
+
+from oracle import core
+from synth import TABLE1_F, configs, fcc_lattice
+
+pytestmark = pytest.mark.gpu
+
+P_CU = configs.cu_params(precision="mixed", skin=0.5, gamma=0.0, temperature=0.0)
+F_GEN = np.array([[1.02, 0.01, 0.0], [0.0, 0.99, 0.015], [0.0, 0.0, 1.005]])
+
+
+@pytest.fixture(scope="module")
+def rc():
+    from paper_1902_09171_amd import rcell
+    rcell.load()
+    return rcell
+
+
+def fro(s):
+    return np.sqrt((s[..., :3] ** 2).sum(-1) + 2 * (s[..., 3:] ** 2).sum(-1))
+
+
+def cu_cells(n, ncell=7, amp=0.05):
+    out = []
+    for k in range(n):
+        x, H = fcc_lattice(ncell)
+        rng = np.random.default_rng(100 + k)
+        out.append(dict(x=x + rng.normal(0.0, amp, x.shape), v=np.zeros_like(x),
+                        bonds=np.zeros((0, 2), np.int32), H0=H))
+    return out
+
+
+def test_copper_statics_matches_oracle_and_cauchy_born(rc):
+    Fs = np.stack([F_GEN] + [TABLE1_F[k] for k in ("B(t)", "C(t)", "C(c)")])
+    cells = cu_cells(len(Fs))
+    g = rc.RCellBatch(P_CU, cells)
+    o = core.OracleBatch(dict(P_CU, precision="fp64"), cells)
+    g.set_deformation(Fs)
+    o.set_deformation(Fs)
+    ftol = 1e-4
+    it_g = g.minimize(20000, ftol)
+    print("gpu iterations", it_g, flush=True)
+    it_o = o.minimize(20000, ftol)
+    pe_g, ke_g = g.get_energy()
+    pe_o, _ = o.get_energy()
+    sg, Pg = g.get_stress(with_P=True)
+    so, Po = o.get_stress(with_P=True)
+    x0, H0 = fcc_lattice(7)
+    n = len(x0)
+    stable = []
+    for k, F in enumerate(Fs):
+        e_cb = core.forces(dict(P_CU, precision="fp64"), F @ H0, x0 @ F.T)[1]
+        print(f"cell {k}: iters gpu {it_g[k]} oracle {it_o[k]}; E/N gpu - CB {(pe_g[k] - e_cb) / n:.2e}, "
+              f"oracle - CB {(pe_o[k] - e_cb) / n:.2e}; stress rel {np.abs(sg[k] - so[k]).max() / fro(so[k]):.2e}",
+              flush=True)
+        assert it_g[k] < 20000
+        assert abs(pe_g[k] - pe_o[k]) / n < 1e-6
+        # the affinely deformed lattice is the minimum only where it is stable (both sides find a
+        # lower state under C(t)); there the GPU must reach the Cauchy-Born energy too
+        if abs(pe_o[k] - e_cb) / n < 1e-6:
+            stable.append(k)
+            assert abs(pe_g[k] - e_cb) / n < 1e-6
+        assert np.abs(sg[k] - so[k]).max() <= 1e-5 * fro(so[k])
+        assert np.abs(Pg[k] - Po[k]).max() <= 3e-5 * np.abs(Po[k]).max()
+        assert np.abs(g.get_forces(k)).max() <= ftol * np.sqrt(3) * 1.01
+    assert np.all(ke_g == 0.0)
+    assert 0 in stable and 1 in stable
+
+
+def test_polymer_statics_reaches_a_minimum(rc):
+    p = configs.kg_params(precision="fp64")
+    cells = [configs.kg_cell([20] * 10, 300 + k) for k in range(2)]
+    g = rc.RCellBatch(p, cells)
+    pe0 = g.get_energy()[0].copy()
+    ftol = 1e-3
+    it = g.minimize(50000, ftol)
+    pe1 = g.get_energy()[0]
+    print("iterations", it, "energy", pe0, "->", pe1, flush=True)
+    assert np.all(it < 50000) and np.all(pe1 < pe0)
+    for k in range(2):
+        s = g.get_state(k)
+        f, pe, _ = core.forces(p, s["H"], s["x"], cells[k]["bonds"])
+        assert np.abs(f).max() <= ftol * np.sqrt(3) * 1.01
+        assert abs(pe - pe1[k]) <= 1e-10 * abs(pe)
+        assert np.all(s["v"] == 0.0)
+
+
+def test_statics_edge_cases_and_md_afterwards(rc):
+    cells = cu_cells(2)
+    g = rc.RCellBatch(P_CU, cells)
+    s0 = g.get_stress()
+    it = g.minimize(0, 1e-4)                    # no move: the stress of the current configuration
+    assert np.all(it == 0)
+    assert np.allclose(g.get_stress(), s0, rtol=1e-12, atol=0)
+    for bad in ((-1, 1e-4), (10, 0.0), (10, -1.0)):
+        with pytest.raises(rc.RCellError):
+            g.minimize(*bad)
+    g.minimize(20000, 1e-4)
+    step = g.get_state(0)["step"]
+    g.run(20)                                   # MD continues from the relaxed state
+    assert g.get_state(0)["step"] == step + 20
+    assert np.all(g.status() == 0)
