@@ -16,6 +16,8 @@ Workloads (``--workload``; every run prints one JSON line):
   kg_batched  512 Kremer-Grest cells of 2k-20k beads (chains of 50-200), each under its own
               rotation x symmetric stretch; mixed precision; a step is 100 MD steps of the whole
               batch followed by the stress read.
+  kg_glassy   100 glassy Kremer-Grest cells of 100 x 100 beads (10^6 beads, the size of the paper's
+              production run) with the LJ attraction to 2.5 sigma at T = 0.1.
   fe_bar      the explicit hex8 bar (8 x 2 x 2 elements, 2 x 2 x 2 Gauss points = 256 r-cells of
               400 x 100 beads, ~10.2 M beads) under uniaxial tension; a step is one FE load step
               (host FE update, F to the cells, 500 MD steps, stress back).
@@ -55,6 +57,7 @@ PAIRS_PER_ATOM = 67           # unique neighbours within 1.95 a in FCC copper
 BYTES_PER_BEAD_STEP = 104
 
 DEFAULTS = {"cu_element": (50, 3), "cu_batched": (10, 2), "kg_single": (1000, 100), "kg_batched": (10, 1),
+            "kg_glassy": (10, 1),
             "fe_bar": (4, 1), "surrogate": (200, 20)}
 
 
@@ -288,15 +291,21 @@ def _fe_bar_cell(c):
     return configs.fe_bar_cells(cells_subset=[c])["cells"][0]
 
 
-def bench_kg_batched(args, torch, rcell, configs):
+def _kg_glassy_cell(c):
+    from synth import configs
+    out = configs.kg_glassy(cells_subset=[c])
+    return out["cells"][0], out["F"][0]
+
+
+def bench_kg_batched(args, torch, rcell, configs, glassy=False):
     import numpy as np
     MD_PER_STEP = 100
-    ncells = 512
+    ncells = 100 if glassy else 512
     log(f"generating {ncells} Kremer-Grest cells")
-    res = make_cells(_kg_batched_cell, list(range(ncells)))
+    res = make_cells(_kg_glassy_cell if glassy else _kg_batched_cell, list(range(ncells)))
     cells = [r[0] for r in res]
     F = np.stack([r[1] for r in res])
-    params = configs.kg_params(precision="mixed")
+    params = configs.kg_glassy_params(precision="mixed") if glassy else configs.kg_params(precision="mixed")
     natoms = sum(len(c["x"]) for c in cells)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -324,14 +333,17 @@ def bench_kg_batched(args, torch, rcell, configs):
     (avg_s, n), _ = kernel_avg(g, 0, lambda: g.run(100))
     check_status(g)
     achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
+    name = "kg_glassy" if glassy else "kg_batched"
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": traffic_from_profiles("k_force_kg", "kg_batched"),
+                "frac": achieved / PEAK_HBM, "traffic": traffic_from_profiles("k_force_kg", name),
                 "kernel": "k_force_kg", "avg_us": avg_s * 1e6, "launches": n,
                 "bytes_per_launch": BYTES_PER_BEAD_STEP * natoms}
-    out = md_line(args, "kg_batched", natoms * MD_PER_STEP * args.steps / elapsed, elapsed, natoms,
-                  {"description": "512 Kremer-Grest cells of 2k-20k beads (chains 50-200, density 0.85), "
-                                  "each under its own rotation x symmetric stretch (eigenvalues 0.9-1.1), "
-                                  "Langevin T = 1, dt 0.005; 100 MD steps per step",
+    what = ("100 glassy Kremer-Grest cells of 100 chains x 100 beads (LJ cut and shifted at 2.5 sigma, "
+            "T = 0.1), each under a small isochoric uniaxial stretch, dt 0.005" if glassy else
+            "512 Kremer-Grest cells of 2k-20k beads (chains 50-200, density 0.85), each under its own "
+            "rotation x symmetric stretch (eigenvalues 0.9-1.1), Langevin T = 1, dt 0.005")
+    out = md_line(args, name, natoms * MD_PER_STEP * args.steps / elapsed, elapsed, natoms,
+                  {"description": what + "; 100 MD steps per step",
                    "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_STEP,
                    "lanes_per_atom": lanes, "rebuilds": g.rebuilds()}, roofline)
     if not args.no_cpu_baseline:
@@ -341,6 +353,10 @@ def bench_kg_batched(args, torch, rcell, configs):
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F[sub], 20,
                                                            s_ora, lanes)
     return out
+
+
+def bench_kg_glassy(args, torch, rcell, configs):
+    return bench_kg_batched(args, torch, rcell, configs, glassy=True)
 
 
 def bench_fe_bar(args, torch, rcell, configs):
@@ -466,7 +482,7 @@ def bench_surrogate(args, torch, rcell, configs):
 
 
 WORKLOADS = {"cu_element": bench_cu_element, "cu_batched": bench_cu_batched, "kg_single": bench_kg_single,
-             "kg_batched": bench_kg_batched,
+             "kg_batched": bench_kg_batched, "kg_glassy": bench_kg_glassy,
              "fe_bar": bench_fe_bar, "surrogate": bench_surrogate}
 
 

@@ -45,6 +45,14 @@ def cu_params(**over):
     return p
 
 
+def kg_glassy_params(**over):
+    """Glassy Kremer-Grest: the LJ attraction kept (cut and shifted at 2.5 sigma) at T = 0.1, below
+    the glass transition (~0.35); otherwise the standard parameters."""
+    p = kg_params(rc=2.5, temperature=0.1)
+    p.update(over)
+    return p
+
+
 def kg_cell(chain_lengths, seed, T=1.0, with_velocities=True):
     x, bonds, H0 = kg_melt(chain_lengths, seed=seed)
     rng = np.random.Generator(np.random.PCG64(seed ^ 0x5A5A5A5A))
@@ -109,6 +117,15 @@ def kg_batched(ncells=512, lo=2000, hi=20000, precision="mixed", cells_subset=No
         F.append(rotated_stretch(generator(s, 3)))
     return dict(name="kg_batched", params=kg_params(precision=precision), cells=cells,
                 F=np.stack(F), steps=1000)
+
+
+def kg_glassy(ncells=100, nchains=100, chain_len=100, precision="mixed", cells_subset=None):
+    """The size of the paper's production run (100 r-cells of 100 chains x 100 beads, 10^6 beads) with
+    the glassy potential; velocities at T = 0.1, each cell under a small isochoric uniaxial stretch."""
+    idx = range(ncells) if cells_subset is None else cells_subset
+    cells = [kg_cell([chain_len] * nchains, cell_seed(MASTER_SEED + 5, c), T=0.1) for c in idx]
+    F = np.stack([uniaxial_isochoric(0.01 * (1 + c % 4), axis=c % 3) for c in idx])
+    return dict(name="kg_glassy", params=kg_glassy_params(precision=precision), cells=cells, F=F)
 
 
 def fe_bar_cells(ncells=256, nchains=400, chain_len=100, precision="mixed", cells_subset=None):

@@ -125,6 +125,30 @@ def test_deformation_qr_remap_parity(rc, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_glassy_kg_forces_stress_and_trajectory(rc, prec):
+    # attractive LJ kept to 2.5 sigma (~60 listed neighbours per bead) at T = 0.1: static forces and
+    # stress after a deformation, then the window stress and positions after 100 Langevin steps
+    cells = [configs.kg_cell([50] * 20, 900 + k, T=0.1) for k in range(2)]
+    p = configs.kg_glassy_params(precision=prec)
+    g = rc.RCellBatch(p, cells)
+    o = core.OracleBatch(p, cells)
+    F = np.stack([configs.uniaxial_isochoric(0.02), np.eye(3)])
+    g.set_deformation(F)
+    o.set_deformation(F)
+    for k in range(2):
+        check_forces(g.get_forces(k), o.get_forces(k), TOL[prec], f"glassy cell {k}")
+    check_stress(g.get_stress(), o.get_stress(), TOL[prec], what="glassy static")
+    g.run(100)
+    o.run(100)
+    check_stress(g.get_stress(), o.get_stress(), TOL[prec], key="s100", what="glassy 100 steps")
+    for k in range(2):
+        d = min_image(g.get_state(k)["x"] - o.get_state(k)["x"], o.get_state(k)["H"])
+        rms = np.sqrt((d ** 2).sum(1).mean())
+        print(f"glassy cell {k} rms dx after 100 steps {rms:.2e}", flush=True)
+        assert rms <= TOL[prec]["x100"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_trajectory_kg_with_langevin(rc, prec):
     cells = kg_cells([[50] * 20])
     p = configs.kg_params(precision=prec)
