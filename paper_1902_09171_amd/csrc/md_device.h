@@ -7,10 +7,12 @@
 //               mixed) or * 2^64 (int64, FP64 mode); .w carries F'(rho) for the EAM force pass.
 //               Differences of two such integers wrap modulo 2^32 (2^64), which is exactly the
 //               per-component minimum image in scaled space: the pair separation needs no
-//               image shifts and no FP64 arithmetic (d = H dS, H as a float hi + lo pair).
+//               image shifts (d = H dS, formed in FP64 and rounded once in mixed precision).
 //   sb          s at the last neighbour build (displacement check)
-//   nbr         Verlet list within rc + skin, column-major nbr[k * npad + i], cell-local j, as
-//               16-bit indices when every cell has at most 65536 atoms (mixed precision), else 32-bit
+//   nbr         Verlet list within rc + skin, cell-local j, as 16-bit indices when every cell has
+//               at most 65536 atoms (mixed precision), else 32-bit; entries of one atom in blocks
+//               of NBLK, the blocks of entries [b NBLK, (b+1) NBLK) of all atoms side by side
+//               (list_index), so a lane loads its UNR entries of a trip with one vector load
 //   bond        up to four FENE partners per atom (cell-local positions, -1 = none)
 //   gid         original cell-local index of the atom stored at each position; pos_of inverts it;
 //               bond0 holds the partners by original index.  At every neighbour build a cell's
@@ -22,12 +24,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rcell {
 
 constexpr int TILE = 64;
 constexpr int BIN_BITS = 10;     // bins per dimension < 2^BIN_BITS (bin coordinates are packed)
 constexpr int BIN_MASK = (1 << BIN_BITS) - 1;
 constexpr int UNR = 4;           // neighbour-loop unroll: gathers in flight per lane
+constexpr int NBLK = 16;         // list block: consecutive entries of one atom (capacity is a multiple)
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWOM32 = 1.0 / 4294967296.0;
 
@@ -36,6 +41,13 @@ enum RedMode : int { RED_START = 0, RED_PRIME = 1, RED_STEP = 2, RED_LAST = 3, R
 enum Status : int { ST_OK = 0, ST_BOND = -4, ST_CAP = -8, ST_BOX = -3, ST_BAD_F = -2 };
 
 struct alignas(32) S64 { long long x, y, z, w; };
+
+// Element index of list entry k of atom i (batch position) in a list of npad atoms: blocks of NBLK
+// consecutive entries of one atom, the blocks of all atoms for entries [b NBLK, (b+1) NBLK) stored
+// together in atom order.  The list holds < 2^32 elements, so 32-bit arithmetic is exact.
+__host__ __device__ inline unsigned list_index(unsigned k, unsigned npad, unsigned i) {
+  return (k / NBLK * npad + i) * NBLK + k % NBLK;
+}
 
 struct CellDev {
   double H[9], Hi[9];             // box (upper triangular) and its inverse
@@ -62,9 +74,16 @@ struct CellDev {
 
 struct Tile { int cell, begin, count, pad; };
 
-// Tile-grid kernels: block w works on tile w (the grid has exactly ntiles blocks).
-__host__ __device__ inline int tile_grid(int ntiles) { return ntiles; }
+// Tile-grid kernels: the grid has ntiles blocks rounded up to a multiple of 8; block w works on
+// tile w (w < ntiles).  The pair kernels use block_tile_xcd instead: the GPU hands consecutive
+// blocks to its 8 XCDs in turn, so XCD x receives blocks x, x + 8, ..., and this mapping gives it
+// the contiguous tile range [x per, (x + 1) per) - whole cells whose positions then stay in that
+// XCD's own L2 for the neighbour gathers.
+__host__ __device__ inline int tile_grid(int ntiles) { return (ntiles + 7) / 8 * 8; }
 __device__ __forceinline__ int block_tile(int ntiles, int block) { return block; }
+__device__ __forceinline__ int block_tile_xcd(int ntiles, int block) {
+  return (block % 8) * ((ntiles + 7) / 8) + block / 8;
+}
 
 struct Part {                     // one tile's contribution
   double W[6], K[6], pe, pad;
@@ -494,24 +513,58 @@ __device__ __forceinline__ void write_part(Part* parts, int part, const double W
 }
 
 // ------------------------------------------------------------------ force kernels
-// UNR neighbours of atom i: list slots k0, k0 + TPA, ...  Slots at or past nn re-read the last
-// entry (in bounds) and come back with ok = false, so the pair loops run straight-line code and
-// mask those slots out.  All UNR index loads, then all UNR gathers, are issued before any
-// arithmetic so that their latencies overlap.  sc points at the cell's first atom.
-template <class P, int TPA, class LT>
-__device__ __forceinline__ void gather_nbrs(const MDArgs& a, const typename P::S* sc, long long i, int nn, int k0,
-                                            typename P::S sj[UNR], bool ok[UNR]) {
-  int jj[UNR];
-  const unsigned np = (unsigned)a.npad, ii = (unsigned)i;   // the list holds < 2^32 entries
-#pragma unroll
-  for (int u = 0; u < UNR; ++u) {
-    const int k = k0 + u * TPA;
-    ok[u] = k < nn;
-    jj[u] = (int)((const LT*)a.nbr)[(unsigned)min(k, nn - 1) * np + ii];
+// List entries of one trip: UNR consecutive entries of one list block, as 32-bit words loaded with
+// one vector load (the trip's first entry is a multiple of UNR, so they are aligned).
+template <class LT>
+struct ListVec {
+  static constexpr int W = UNR * (int)sizeof(LT) / 4;
+  static_assert(W == 1 || W == 2 || W == 4, "one vector load per trip");
+  uint32_t w[W];
+  __device__ void load(const LT* p) {
+    if constexpr (W == 1) {
+      w[0] = *(const uint32_t*)p;
+    } else if constexpr (W == 2) {
+      const uint2 v = *(const uint2*)p;
+      w[0] = v.x; w[1] = v.y;
+    } else {
+      const uint4 v = *(const uint4*)p;
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    }
   }
+  __device__ int get(int u) const {
+    if constexpr (sizeof(LT) == 2) return (int)((w[u >> 1] >> ((u & 1) * 16)) & 0xffffu);
+    else return (int)w[u];
+  }
+};
+static_assert(NBLK % UNR == 0, "a trip's entries must lie in one list block");
+
+// One lane's walk over atom i's list.  Per trip the lane takes UNR consecutive entries (one vector
+// load) and the TPA lanes of the atom take consecutive groups of UNR.  The next trip's entries are
+// requested right after this trip's gathers are issued, so a trip waits for one memory round trip
+// (the gathers), not two.  Entries at or past nn gather the cell's first atom and come back with
+// ok = false: the pair loops run straight-line code and mask those slots out.  sc points at the
+// cell's first atom.
+template <class P, int TPA, class LT>
+struct NbrWalk {
+  const LT* list;
+  unsigned np, ii;
+  int nn, k0;
+  ListVec<LT> nx;
+  __device__ NbrWalk(const MDArgs& a, long long i, int nn_, int lane)
+      : list((const LT*)a.nbr), np((unsigned)a.npad), ii((unsigned)i), nn(nn_), k0(lane * UNR), nx{} {
+    if (k0 < nn) nx.load(list + list_index((unsigned)k0, np, ii));
+  }
+  __device__ bool more() const { return k0 < nn; }
+  __device__ void next(const typename P::S* sc, typename P::S sj[UNR], bool ok[UNR]) {
 #pragma unroll
-  for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, jj[u]);
-}
+    for (int u = 0; u < UNR; ++u) {
+      ok[u] = k0 + u < nn;
+      sj[u] = P::load_rel(sc, ok[u] ? nx.get(u) : 0);
+    }
+    k0 += UNR * TPA;
+    if (k0 < nn) nx.load(list + list_index((unsigned)k0, np, ii));
+  }
+};
 
 // Kremer-Grest: LJ truncated and shifted at rc on every listed pair + FENE on bonds; then the
 // integration tail.  TPA lanes share one atom's neighbour list.
@@ -520,7 +573,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
   __shared__ PartShared<NT / 64> psh;
-  const int tb = block_tile(a.ntiles, blockIdx.x);
+  const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
   if (tb >= a.ntiles) return;
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
@@ -536,28 +589,32 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     const R rc2 = (R)a.rc2, sig2 = (R)a.lj_sig2, e24 = (R)(24.0 * a.lj_eps), e4 = (R)(4.0 * a.lj_eps), sh = (R)a.lj_shift;
     const typename P::Geo g = P::geo(C);
     const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
-    // neighbours k = lane, lane + TPA, ... in that order
-    for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
-      typename P::S sj[UNR];
-      bool ok[UNR];
-      gather_nbrs<P, TPA, LT>(a, sc, i, nn, k0, sj, ok);
+    // the pair energy is summed only where it is reported: not in the middle steps of a run
+    auto pairs = [&](auto with_pe) {
+      for (NbrWalk<P, TPA, LT> walk(a, i, nn, lane); walk.more();) {
+        typename P::S sj[UNR];
+        bool ok[UNR];
+        walk.next(sc, sj, ok);
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        R d[3];
-        P::sep(sj[u], si, g, d);
-        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const bool in = ok[u] && r2 < rc2;
-        const R r2i = P::rcp(r2);
-        const R s2 = sig2 * r2i;
-        const R s6 = s2 * s2 * s2;
-        const R gr = in ? -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i : (R)0;   // (dU/dr) / r
-        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-        const R hg = (R)0.5 * gr;
-        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
-        pe += in ? (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh) : (R)0;
+        for (int u = 0; u < UNR; ++u) {
+          R d[3];
+          P::sep(sj[u], si, g, d);
+          const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          const bool in = ok[u] && r2 < rc2;
+          const R r2i = P::rcp(r2);
+          const R s2 = sig2 * r2i;
+          const R s6 = s2 * s2 * s2;
+          const R gr = in ? -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i : (R)0;   // (dU/dr) / r
+          f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+          const R hg = (R)0.5 * gr;
+          w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+          w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+          if constexpr (decltype(with_pe)::value) pe += in ? (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh) : (R)0;
+        }
       }
-    }
+    };
+    if (mode == MODE_STEP || mode == MODE_DRY) pairs(std::false_type{});
+    else pairs(std::true_type{});
     if (lane == 0) {
       const int4 b = a.bond[i];
       const int bp[4] = {b.x, b.y, b.z, b.w};
@@ -606,7 +663,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
 template <class P, int TPA, int SN, int SM, class LT>
 __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   using R = typename P::R;
-  const int tb = block_tile(a.ntiles, blockIdx.x);
+  const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
   if (tb >= a.ntiles) return;
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
@@ -620,10 +677,10 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, rhoc = (R)a.sc_rhoc;
     const typename P::Geo g = P::geo(C);
     const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
-    for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
+    for (NbrWalk<P, TPA, LT> walk(a, i, nn, lane); walk.more();) {
       typename P::S sj[UNR];
       bool ok[UNR];
-      gather_nbrs<P, TPA, LT>(a, sc, i, nn, k0, sj, ok);
+      walk.next(sc, sj, ok);
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         R d[3];
@@ -648,7 +705,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   using R = typename P::R;
   constexpr int NT = TILE * TPA;
   __shared__ PartShared<NT / 64> psh;
-  const int tb = block_tile(a.ntiles, blockIdx.x);
+  const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
   if (tb >= a.ntiles) return;
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
@@ -665,28 +722,33 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     const R eh = (R)(0.5 * a.sc_eps), phic = (R)a.sc_phic;
     const typename P::Geo g = P::geo(C);
     const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
-    for (int k0 = lane; k0 < nn; k0 += UNR * TPA) {
-      typename P::S sj[UNR];
-      bool ok[UNR];
-      gather_nbrs<P, TPA, LT>(a, sc, i, nn, k0, sj, ok);
+    // the pair energy is summed only where it is reported: not in the middle steps of a run
+    auto pairs = [&](auto with_pe) {
+      for (NbrWalk<P, TPA, LT> walk(a, i, nn, lane); walk.more();) {
+        typename P::S sj[UNR];
+        bool ok[UNR];
+        walk.next(sc, sj, ok);
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        R d[3];
-        P::sep(sj[u], si, g, d);
-        const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        const bool in = ok[u] && r2 < rc2;
-        const R ri = P::rsq(r2);
-        R tn, tm;
-        sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
-        const R g0 = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
-        const R gr = in ? g0 : (R)0;
-        f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-        const R hg = (R)0.5 * gr;
-        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
-        pe += in ? eh * (tn - phic) : (R)0;
+        for (int u = 0; u < UNR; ++u) {
+          R d[3];
+          P::sep(sj[u], si, g, d);
+          const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          const bool in = ok[u] && r2 < rc2;
+          const R ri = P::rsq(r2);
+          R tn, tm;
+          sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
+          const R g0 = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
+          const R gr = in ? g0 : (R)0;
+          f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
+          const R hg = (R)0.5 * gr;
+          w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
+          w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+          if constexpr (decltype(with_pe)::value) pe += in ? eh * (tn - phic) : (R)0;
+        }
       }
-    }
+    };
+    if (mode == MODE_STEP || mode == MODE_DRY) pairs(std::false_type{});
+    else pairs(std::true_type{});
   }
   double W[6], K[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
@@ -699,7 +761,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) W[q] = 0.0;
     PE = 0.0;
-  } else if (active) {
+  } else if (active && mode != MODE_STEP && mode != MODE_DRY) {
     // embedding energy -eps c sqrt(rho) = (eps c)^2 / (2 F'(rho)), zero where rho = 0
     const double ec = a.sc_eps * a.sc_c;
     if (fpi != (R)0) PE += ec * ec / (2.0 * (double)fpi);
@@ -877,7 +939,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   const double kin = a.include_kinetic ? 1.0 : 0.0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) s[q] = (r[q] - kin * r[6 + q]) / C.V;
-  C.pe = r[12];
+  if (mode != RED_STEP) C.pe = r[12];      // the middle steps of a run do not sum the energy
   if (mode == RED_PRIME) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) C.last[q] = s[q];
@@ -1237,11 +1299,11 @@ __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
   const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
   if (!over) {
     for (int e = 0; e < mine; ++e)
-      if (base + e < a.maxnb) ((LT*)a.nbr)[(unsigned)(base + e) * np + ii] = (LT)stash[e * NT + threadIdx.x];
+      if (base + e < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)(base + e), np, ii)] = (LT)stash[e * NT + threadIdx.x];
   } else {
     int k = base;
     scan_bins([&](int lj) {
-      if (k < a.maxnb) ((LT*)a.nbr)[(unsigned)k * np + ii] = (LT)lj;
+      if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii)] = (LT)lj;
       ++k;
     });
   }

@@ -411,6 +411,7 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
 }
 
 int ensure_list_capacity(rcell_ctx* c, int need) {
+  need = (need + NBLK - 1) / NBLK * NBLK;          // whole list blocks
   if (need <= c->maxnb) return RCELL_OK;
   // the pair loops address the list with 32-bit element indices
   if ((unsigned long long)need * (unsigned long long)c->npad >= (1ull << 32))
