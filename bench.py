@@ -21,20 +21,28 @@ Workloads (``--workload``; every run prints one JSON line):
   fe_bar      the explicit hex8 bar (8 x 2 x 2 elements, 2 x 2 x 2 Gauss points = 256 r-cells of
               400 x 100 beads, ~10.2 M beads) under uniaxial tension; a step is one FE load step
               (host FE update, F to the cells, 500 MD steps, stress back).
+  fe_tet      the paper's polymer specimen (Sec. 3.2): a cube of 100 C3D4 tetrahedra with one
+              quadrature point each = 100 r-cells of 100 x 100 beads (10^6 beads), uniaxial tension;
+              a step is one FE load step with 500 MD steps.
+  fe_scaling  the system of the paper's scaling test on one GPU: 1000 C3D4 tetrahedra = 1000 r-cells
+              of 100 x 100 beads (10^7 beads); a step is one FE load step with 100 MD steps.
   surrogate   the stress surrogate network (153 -> 4 x 256 -> 6, ensemble of 5, BF16 matrix cores
               with FP32 accumulation): ensemble evaluations per second at the bar's batch (256
               Gauss points) and at a large batch, and training samples per second.
 
 Inputs are resident in HBM before the timed region; timings bracket K steps with device
-synchronisation.  The roofline object describes the dominant kernel, timed with HIP events on
-the library's own stream.  The CPU baseline is the FP64 oracle on a bounded sample of the same
-workload, on this host's cores.
+synchronisation.  The roofline object describes the dominant kernel, timed in a separate pass with
+the start and stop events of its own dispatches on the library's stream, and, after the timed
+region, the copy bandwidth and FP32 FMA rate this GPU delivers (measured_peaks).  The CPU baseline
+is the FP64 oracle on a bounded sample of the same workload (about ORACLE_SECONDS of CPU time), on
+this host's cores.
 
   python bench.py [--workload W] [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -56,9 +64,10 @@ PAIRS_PER_ATOM = 67           # unique neighbours within 1.95 a in FCC copper
 # written (96 B), plus the two chain partners as 32-bit indices (8 B)
 BYTES_PER_BEAD_STEP = 104
 
+ORACLE_SECONDS = 10.0     # CPU time the oracle baseline runs for (bounded sample of the workload)
 DEFAULTS = {"cu_element": (50, 3), "cu_batched": (10, 2), "kg_single": (1000, 100), "kg_batched": (10, 1),
             "kg_glassy": (10, 1),
-            "fe_bar": (4, 1), "surrogate": (200, 20)}
+            "fe_bar": (4, 1), "fe_tet": (4, 1), "fe_scaling": (3, 1), "surrogate": (200, 20)}
 
 
 def kernel_source_hash():
@@ -92,10 +101,13 @@ def log(msg):
 
 
 # ------------------------------------------------------------------ MD helpers
-def oracle_sample(params, cells, F, nsteps, label):
-    """The FP64 oracle on the host cores: nsteps MD steps of the given cells after set_deformation(F).
-    Returns (cpu_baseline dict, oracle stress)."""
+def oracle_sample(params, cells, F, nsteps, label, seconds=None):
+    """The FP64 oracle on the host cores: MD steps of the given cells after set_deformation(F).  The
+    stress window of the first nsteps is returned for the comparison with the GPU; the oracle then
+    runs on until about `seconds` of CPU time (ORACLE_SECONDS) have been spent, and the rate is taken
+    over every step.  Returns (cpu_baseline dict, oracle stress after nsteps)."""
     from oracle import core
+    seconds = ORACLE_SECONDS if seconds is None else seconds
     threads = core.threads(min(len(cells), os.cpu_count() or 1))
     ob = core.OracleBatch(params, cells)
     ob.set_deformation(F)
@@ -103,9 +115,17 @@ def oracle_sample(params, cells, F, nsteps, label):
     t0 = time.perf_counter()
     ob.run(nsteps)
     dt = time.perf_counter() - t0
+    s_ora = ob.get_stress()
+    extra = min(100 * nsteps, max(0, math.ceil((seconds - dt) / (dt / nsteps))))
+    if extra:
+        t1 = time.perf_counter()
+        ob.run(extra)
+        dt += time.perf_counter() - t1
     natoms = sum(len(c["x"]) for c in cells)
-    return dict(value=natoms * nsteps / dt, unit="atom-steps/s", cores=threads, kind="oracle",
-                sample=f"{len(cells)} cells, {natoms} atoms, {nsteps} MD steps ({label})"), ob.get_stress()
+    total = nsteps + extra
+    return dict(value=natoms * total / dt, unit="atom-steps/s", cores=threads, kind="oracle",
+                sample=f"{len(cells)} cells, {natoms} atoms, {total} MD steps in {dt:.1f} s ({label}; "
+                       f"stress compared with the GPU after the first {nsteps})"), s_ora
 
 
 def gpu_sample_error(rcell, params, cells, F, nsteps, s_ora, lanes):
@@ -291,6 +311,16 @@ def _fe_bar_cell(c):
     return configs.fe_bar_cells(cells_subset=[c])["cells"][0]
 
 
+def _fe_tet_cell(c):
+    from synth import configs
+    return configs.fe_tet_cells(cells_subset=[c])["cells"][0]
+
+
+def _fe_scaling_cell(c):
+    from synth import configs
+    return configs.fe_tet_cells(cells_subset=[c], stream=6)["cells"][0]
+
+
 def _kg_glassy_cell(c):
     from synth import configs
     out = configs.kg_glassy(cells_subset=[c])
@@ -359,20 +389,36 @@ def bench_kg_glassy(args, torch, rcell, configs):
     return bench_kg_batched(args, torch, rcell, configs, glassy=True)
 
 
-def bench_fe_bar(args, torch, rcell, configs):
+# The FE workloads: mesh, r-cell generator, MD steps per load step and the text of the line.
+FE_WORKLOADS = {
+    "fe_bar": dict(mesh=("hex8", (8, 2, 2), (200.0, 50.0, 50.0), 0.95), cell=_fe_bar_cell, md=500,
+                   text="explicit hex8 bar 8x2x2 elements x 8 Gauss points = 256 Kremer-Grest r-cells of 400 "
+                        "chains x 100 beads, imperfection-seeded neck"),
+    "fe_tet": dict(mesh=("tet4", (5, 2, 2), (150.0, 150.0, 150.0), 1.0), cell=_fe_tet_cell, md=500,
+                   text="the paper's cubic polymer specimen: 100 C3D4 tetrahedra, one quadrature point each = 100 "
+                        "Kremer-Grest r-cells of 100 chains x 100 beads (10^6 beads)"),
+    "fe_scaling": dict(mesh=("tet4", (8, 5, 5), (200.0, 200.0, 200.0), 1.0), cell=_fe_scaling_cell, md=100,
+                       text="the paper's scaling system on one GPU: 1000 C3D4 tetrahedra = 1000 Kremer-Grest "
+                            "r-cells of 100 chains x 100 beads (10^7 beads)"),
+}
+
+
+def bench_fe(args, torch, rcell, configs, name):
     import numpy as np
     from paper_1902_09171_amd import fe
-    MD_PER_LOAD = 500
-    mesh = fe.Hex8Bar(nel=(8, 2, 2), size=(200.0, 50.0, 50.0), rho0=0.85, imperfection=0.95)
-    log(f"generating {mesh.ngp} r-cells of 40000 beads")
-    cells = make_cells(_fe_bar_cell, list(range(mesh.ngp)))
+    spec = FE_WORKLOADS[name]
+    MD_PER_LOAD = spec["md"]
+    kind, nel, size, imp = spec["mesh"]
+    mesh = (fe.Hex8Bar if kind == "hex8" else fe.Tet4Bar)(nel=nel, size=size, rho0=0.85, imperfection=imp)
+    log(f"generating {mesh.ngp} r-cells")
+    cells = make_cells(spec["cell"], list(range(mesh.ngp)))
     params = configs.kg_params(precision="mixed")
     natoms = sum(len(c["x"]) for c in cells)
     log(f"creating the batch: {natoms} beads")
     md = fe.MDStress(params, cells, MD_PER_LOAD)
     lanes = md.g.set_lanes(args.lanes)
     dt = MD_PER_LOAD * params["dt"]
-    # 100 % nominal strain over 100 load steps
+    # 1 % nominal strain per load step
     bar = fe.ExplicitBar(mesh, md, dt=dt, pull_velocity=0.01 * mesh.size[0] / dt, damping=0.2)
     for _ in range(args.warmup):
         bar.step()
@@ -387,20 +433,19 @@ def bench_fe_bar(args, torch, rcell, configs):
     check_status(md.g)
     achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": traffic_from_profiles("k_force_kg", "fe_bar"),
+                "frac": achieved / PEAK_HBM, "traffic": traffic_from_profiles("k_force_kg", name),
                 "kernel": "k_force_kg", "avg_us": avg_s * 1e6, "launches": n,
                 "bytes_per_launch": BYTES_PER_BEAD_STEP * natoms}
-    out = md_line(args, "fe_bar", natoms * MD_PER_LOAD * args.steps / elapsed, elapsed, natoms,
-                  {"description": "explicit hex8 bar 8x2x2 elements x 8 Gauss points = 256 Kremer-Grest "
-                                  "r-cells of 400 chains x 100 beads, imperfection-seeded neck, 1 % nominal "
-                                  "strain per load step, 500 MD steps per load step",
+    out = md_line(args, name, natoms * MD_PER_LOAD * args.steps / elapsed, elapsed, natoms,
+                  {"description": spec["text"] + f", 1 % nominal strain per load step, {MD_PER_LOAD} MD steps "
+                                                 "per load step",
                    "cells": mesh.ngp, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
                    "lanes_per_atom": lanes, "rebuilds": md.g.rebuilds()}, roofline,
                   extra={"fe_wall_s_per_load_step": elapsed / args.steps})
     if not args.no_cpu_baseline:
         sub = list(range(4))
         F = np.stack([np.eye(3)] * len(sub))
-        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F, 20, "4 of the bar's cells, 20 MD steps")
+        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F, 20, "4 of the r-cells, from rest")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F, 20,
                                                            s_ora, lanes)
@@ -483,10 +528,12 @@ def bench_surrogate(args, torch, rcell, configs):
 
 WORKLOADS = {"cu_element": bench_cu_element, "cu_batched": bench_cu_batched, "kg_single": bench_kg_single,
              "kg_batched": bench_kg_batched, "kg_glassy": bench_kg_glassy,
-             "fe_bar": bench_fe_bar, "surrogate": bench_surrogate}
+             "fe_bar": lambda *a: bench_fe(*a, name="fe_bar"), "fe_tet": lambda *a: bench_fe(*a, name="fe_tet"),
+             "fe_scaling": lambda *a: bench_fe(*a, name="fe_scaling"), "surrogate": bench_surrogate}
 
 
 def main():
+    global ORACLE_SECONDS
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="cu_element", choices=sorted(WORKLOADS))
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +541,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=25)
+    ap.add_argument("--no-peak-probe", action="store_true",
+                    help="skip the copy / FMA probe that reports measured peaks")
+    ap.add_argument("--cpu-seconds", type=float, default=ORACLE_SECONDS,
+                    help="CPU time of the oracle baseline sample")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0 = autotune)")
     ap.add_argument("--skin", type=float, default=None,
                     help="neighbour skin override for the MD workloads (changes speed, never the pairs within rc)")
@@ -504,6 +555,7 @@ def main():
         print(json.dumps({"error": "the r-cell library runs on one GPU; sharding the cells "
                                    "over several GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
+    ORACLE_SECONDS = args.cpu_seconds
     d_steps, d_warm = DEFAULTS[args.workload]
     args.steps = d_steps if args.steps is None else args.steps
     args.warmup = d_warm if args.warmup is None else args.warmup
@@ -528,6 +580,16 @@ def main():
     out = WORKLOADS[args.workload](args, torch, rcell, configs)
     if args.skin is not None:
         out["config"]["skin"] = args.skin
+    if not args.no_peak_probe:
+        # after the timed region: the peaks this GPU delivers, beside the published ones
+        gbs, tf = rcell.probe_peaks(1 << 30, torch.cuda.current_stream().cuda_stream)
+        r = out["roofline"]
+        r["measured_peaks"] = {"copy_GBs": gbs, "fp32_fma_TFLOPs": tf,
+                               "probe": "1 GiB device copy (read + write) and FP32 FMA chains on every CU, "
+                                        "non-packed as in the MD kernels"}
+        meas = {"hbm": gbs, "alu": tf}.get(r["bound"])
+        if meas:
+            r["frac_of_measured_peak"] = r["achieved"] / meas
     print(json.dumps(out), flush=True)
 
 

@@ -23,6 +23,7 @@
  */
 #ifndef RCELL_H
 #define RCELL_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -162,9 +163,11 @@ int rcell_get_lanes(rcell_ctx* ctx, int32_t* lanes);
  * 10); 0 launches every kernel individually.  Results are identical either way. */
 int rcell_set_graph_steps(rcell_ctx* ctx, int32_t steps);
 /* kernel timing: while enabled, each launch of the pair-force pass (which = 0: the force kernel
- * with the fused Langevin/Verlet update; which = 1: the EAM density pass) is bracketed by HIP
- * events on the context's stream (8192 events are created when enabling; graphs are not used).  rcell_prof_read synchronises, returns the summed duration in
- * milliseconds and the number of launches since the last read, and resets both. */
+ * with the fused Langevin/Verlet update; which = 1: the EAM density pass) carries the start and
+ * stop HIP events of its own dispatch (hipExtLaunchKernel: the kernel's duration, without launch
+ * latency), on the context's stream; 8192 events are created when enabling, and graphs are not
+ * used meanwhile.  rcell_prof_read synchronises, returns the summed duration in milliseconds and
+ * the number of launches since the last read, and resets both. */
 int rcell_prof_enable(rcell_ctx* ctx, int32_t on);
 int rcell_prof_read(rcell_ctx* ctx, int32_t which, double* total_ms, int64_t* launches);
 
@@ -178,6 +181,15 @@ int rcell_qr_dev(const void* F_dev, int32_t n, void* Q_dev, void* R_dev, void* s
  * for a bad F.  Used by the surrogate path, whose stresses come from the network. */
 int rcell_stress_return_dev(const void* F_dev, const void* sigma_md_dev, int32_t n, void* sigma_fem_dev, void* P_dev,
                             void* hip_stream);
+
+/* ---- measured machine peaks (no context) ---- */
+/* Times, on hip_stream (NULL = null stream), a device copy of copy_bytes (read + write; two
+ * buffers of that size are allocated and freed) and independent FP32 FMA chains on every CU (built
+ * without packed FP32, like the MD kernels), each after one warm-up launch.  copy_gbs receives the
+ * copy's read + write bandwidth in GB/s, fma_tflops the FP32 FMA rate in TFLOP/s (FMA = 2 FLOP).
+ * Synchronises.  RCELL_ERR_ARG for null outputs or copy_bytes < 16, RCELL_ERR_OOM if the buffers
+ * cannot be allocated. */
+int rcell_probe_peaks(size_t copy_bytes, double* copy_gbs, double* fma_tflops, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librcell.so")
-SOURCES = ["rcell_md.hip", "rsur.hip"]
+SOURCES = ["rcell_md.hip", "rsur.hip", "rcell_probe.hip"]
 HEADERS = ["md_device.h", "rsur_device.h"]
 
 FLAGS = [

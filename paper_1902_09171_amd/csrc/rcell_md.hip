@@ -2,6 +2,7 @@
 // argument marshalling (AoS <-> SoA), and the launch sequence of every call.  All arithmetic of
 // the method runs in the kernels of md_device.h.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -224,39 +225,40 @@ hipEvent_t prof_event(rcell_ctx* c) {
   return e;
 }
 
-// record an event pair around one launch of pass `which` when timing is enabled
-struct ProfScope {
-  rcell_ctx* c;
-  int which;
-  hipEvent_t e0 = nullptr;
-  ProfScope(rcell_ctx* c_, int w) : c(c_), which(w) {
-    if (c->prof && (e0 = prof_event(c))) (void)hipEventRecord(e0, c->stream);
+// Timing of the pair passes (rcell_prof_*): the start and stop events are those of the kernel
+// dispatch itself (hipExtLaunchKernel), so a pair holds the kernel's own duration, without the
+// queue and launch latency that events recorded around the launch would add.
+bool prof_pair(rcell_ctx* c, hipEvent_t* e0, hipEvent_t* e1) {
+  if (!c->prof || !(*e0 = prof_event(c))) return false;
+  if (!(*e1 = prof_event(c))) {
+    c->ev_pool.push_back(*e0);
+    return false;
   }
-  ~ProfScope() {
-    if (!e0) return;
-    hipEvent_t e1 = prof_event(c);
-    if (!e1) { c->ev_pool.push_back(e0); return; }
-    (void)hipEventRecord(e1, c->stream);
-    c->prof_ev[which].push_back({e0, e1});
-  }
-};
+  return true;
+}
+
+#define LAUNCH_PASS(c, which, kernel, grid, block, ...)                                      \
+  do {                                                                                       \
+    hipEvent_t e0_ = nullptr, e1_ = nullptr;                                                 \
+    if (prof_pair(c, &e0_, &e1_)) {                                                          \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, (c)->stream, e0_, e1_, 0, __VA_ARGS__);  \
+      (c)->prof_ev[which].push_back({e0_, e1_});                                             \
+    } else {                                                                                 \
+      hipLaunchKernelGGL(kernel, grid, block, 0, (c)->stream, __VA_ARGS__);                  \
+    }                                                                                        \
+  } while (0)
 
 template <class P, int TPA, int SN, int SM, class LT>
 void force_eam_t(rcell_ctx* c, const MDArgs& a, int mode) {
   const dim3 grid(tile_grid(c->ntiles)), block(TILE * TPA);
-  {
-    ProfScope ps(c, 1);
-    hipLaunchKernelGGL((k_eam_rho<P, TPA, SN, SM, LT>), grid, block, 0, c->stream, a, mode);
-  }
-  ProfScope ps(c, 0);
-  hipLaunchKernelGGL((k_force_eam<P, TPA, SN, SM, LT>), grid, block, 0, c->stream, a, mode);
+  LAUNCH_PASS(c, 1, (k_eam_rho<P, TPA, SN, SM, LT>), grid, block, a, mode);
+  LAUNCH_PASS(c, 0, (k_force_eam<P, TPA, SN, SM, LT>), grid, block, a, mode);
 }
 
 template <class P, int TPA, class LT>
 void force_t(rcell_ctx* c, const MDArgs& a, int mode) {
   if (c->p.potential == RCELL_POT_KG) {
-    ProfScope ps(c, 0);
-    hipLaunchKernelGGL((k_force_kg<P, TPA, LT>), dim3(tile_grid(c->ntiles)), dim3(TILE * TPA), 0, c->stream, a, mode);
+    LAUNCH_PASS(c, 0, (k_force_kg<P, TPA, LT>), dim3(tile_grid(c->ntiles)), dim3(TILE * TPA), a, mode);
   } else if (a.sc_n == 9 && a.sc_m == 6) {      // copper, nickel: exponents fixed at compile time
     force_eam_t<P, TPA, 9, 6, LT>(c, a, mode);
   } else {

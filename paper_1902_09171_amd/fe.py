@@ -1,6 +1,8 @@
 """Host finite-element driver of the coupling (Sec. 2.2, Eqs. 10-14; Fig. 1): an explicit
-total-Lagrangian hex8 bar whose quadrature points take their first Piola-Kirchhoff stress from a
-stress provider - batched MD r-cells (rcell) or the learned surrogate.
+total-Lagrangian bar whose quadrature points take their first Piola-Kirchhoff stress from a
+stress provider - batched MD r-cells (rcell) or the learned surrogate.  Two meshes: trilinear
+hex8 bricks with 2x2x2 Gauss points, and linear four-node tetrahedra (C3D4, one quadrature point
+each), the element of the paper's polymer specimen (Sec. 3.2) and scaling test.
 
 Per load step: F at every Gauss point from the nodal displacements (F = I + du/dX), P from the
 provider, internal forces f_int = sum_gp B^T P w det J0 (Eq. 12), lumped mass (Eq. 11), and a
@@ -26,7 +28,42 @@ def shape(xi):
     return N, dN
 
 
-class Hex8Bar:
+class _Mesh:
+    """What the bar integrator needs from a mesh: nodes X, connectivity conn, and per quadrature
+    point its element gp_elem, dN/dX (B), weight x det J0 (wdet); lumped nodal masses."""
+
+    def deformation_gradients(self, u):
+        """F = I + sum_a u_a (x) dN_a/dX at every quadrature point, (ngp, 3, 3)."""
+        ue = u[self.conn[self.gp_elem]]             # (ngp, nodes per element, 3)
+        return np.eye(3)[None] + np.einsum("gai,gaj->gij", ue, self.B)
+
+    def internal_forces(self, P):
+        """f_int_a = sum_gp P . dN_a/dX w det J0 (Eq. 12), (nnodes, 3)."""
+        fe = np.einsum("gij,gaj->gai", P, self.B) * self.wdet[:, None, None]
+        f = np.zeros((self.nnodes, 3))
+        np.add.at(f, self.conn[self.gp_elem].ravel(), fe.reshape(-1, 3))
+        return f
+
+    def face(self, axis, side):
+        lo, hi = self.X[:, axis].min(), self.X[:, axis].max()
+        return np.where(np.isclose(self.X[:, axis], hi if side else lo))[0]
+
+
+def _grid_nodes(nel, size, imperfection):
+    """Nodes of a structured grid of nx x ny x nz bricks on [0, Lx] x [0, Ly] x [0, Lz]; with
+    imperfection < 1 the middle cross-section (x = Lx / 2) is scaled laterally about the axis."""
+    nx, ny, nz = nel
+    Lx, Ly, Lz = size
+    xs, ys, zs = np.linspace(0, Lx, nx + 1), np.linspace(0, Ly, ny + 1), np.linspace(0, Lz, nz + 1)
+    X = np.array([[x, y, z] for x in xs for y in ys for z in zs])
+    if imperfection != 1.0 and nx % 2 == 0:
+        mid = np.isclose(X[:, 0], xs[nx // 2])
+        X[mid, 1] = Ly / 2 + (X[mid, 1] - Ly / 2) * imperfection
+        X[mid, 2] = Lz / 2 + (X[mid, 2] - Lz / 2) * imperfection
+    return X, (lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k)
+
+
+class Hex8Bar(_Mesh):
     """Structured nx x ny x nz hex8 mesh of a bar [0, Lx] x [0, Ly] x [0, Lz], 2x2x2 Gauss points.
 
     imperfection < 1 scales the lateral coordinates of the middle cross-section about the bar axis
@@ -34,15 +71,8 @@ class Hex8Bar:
 
     def __init__(self, nel=(8, 2, 2), size=(200.0, 50.0, 50.0), rho0=0.85, imperfection=1.0):
         nx, ny, nz = nel
-        Lx, Ly, Lz = size
         self.nel, self.size, self.rho0 = nel, size, rho0
-        xs, ys, zs = np.linspace(0, Lx, nx + 1), np.linspace(0, Ly, ny + 1), np.linspace(0, Lz, nz + 1)
-        self.node = lambda i, j, k: (i * (ny + 1) + j) * (nz + 1) + k
-        X = np.array([[x, y, z] for x in xs for y in ys for z in zs])
-        if imperfection != 1.0 and nx % 2 == 0:
-            mid = np.isclose(X[:, 0], xs[nx // 2])
-            X[mid, 1] = Ly / 2 + (X[mid, 1] - Ly / 2) * imperfection
-            X[mid, 2] = Lz / 2 + (X[mid, 2] - Lz / 2) * imperfection
+        X, self.node = _grid_nodes(nel, size, imperfection)
         self.X = X
         self.nnodes = len(X)
         conn = []
@@ -73,21 +103,59 @@ class Hex8Bar:
             np.add.at(self.mass, self.conn[self.gp_elem[g]], rho0 * Ns[g] * self.wdet[g])
         self.volume = self.wdet.sum()
 
-    def deformation_gradients(self, u):
-        """F = I + sum_a u_a (x) dN_a/dX at every Gauss point, (ngp, 3, 3)."""
-        ue = u[self.conn[self.gp_elem]]             # (ngp, 8, 3)
-        return np.eye(3)[None] + np.einsum("gai,gaj->gij", ue, self.B)
 
-    def internal_forces(self, P):
-        """f_int_a = sum_gp P . dN_a/dX w det J0 (Eq. 12), (nnodes, 3)."""
-        fe = np.einsum("gij,gaj->gai", P, self.B) * self.wdet[:, None, None]
-        f = np.zeros((self.nnodes, 3))
-        np.add.at(f, self.conn[self.gp_elem].ravel(), fe.reshape(-1, 3))
-        return f
 
-    def face(self, axis, side):
-        lo, hi = self.X[:, axis].min(), self.X[:, axis].max()
-        return np.where(np.isclose(self.X[:, axis], hi if side else lo))[0]
+# the four nodes of a linear tetrahedron in natural coordinates: N = (1 - xi - eta - zeta, xi, eta, zeta)
+_DN_TET = np.array([[-1.0, -1.0, -1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+
+
+class Tet4Bar(_Mesh):
+    """Linear four-node tetrahedra (C3D4) on a structured grid of nx x ny x nz bricks of the bar
+    [0, Lx] x [0, Ly] x [0, Lz]: five tetrahedra per brick, one quadrature point per tetrahedron
+    (constant strain), lumped mass a quarter of the element mass per node.
+
+    Each brick is split into the tetrahedron spanned by its four corners of even global index
+    parity (i + j + k) and the four corner tetrahedra of its odd corners, each with that corner's
+    three neighbours along the brick edges.  Every face diagonal then joins the two even corners of
+    the face on both sides, so the mesh is conforming.  2 x 2 x 5 bricks give the 100 elements of
+    the paper's cubic polymer specimen (Sec. 3.2)."""
+
+    def __init__(self, nel=(5, 2, 2), size=(22.7, 22.7, 22.7), rho0=0.85, imperfection=1.0):
+        nx, ny, nz = nel
+        self.nel, self.size, self.rho0 = nel, size, rho0
+        X, self.node = _grid_nodes(nel, size, imperfection)
+        self.X = X
+        self.nnodes = len(X)
+        corners = [(a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+        conn = []
+        for i in range(nx):
+            for j in range(ny):
+                for k in range(nz):
+                    gid = {t: self.node(i + t[0], j + t[1], k + t[2]) for t in corners}
+                    even = [t for t in corners if (i + t[0] + j + t[1] + k + t[2]) % 2 == 0]
+                    odd = [t for t in corners if (i + t[0] + j + t[1] + k + t[2]) % 2 == 1]
+                    tets = [even]
+                    for t in odd:
+                        nb = [u for u in even if sum(abs(u[q] - t[q]) for q in range(3)) == 1]
+                        tets.append([t] + nb)
+                    for tet in tets:
+                        ids = [gid[t] for t in tet]
+                        if np.linalg.det((X[ids[1:]] - X[ids[0]]).T) < 0:
+                            ids[1], ids[2] = ids[2], ids[1]      # positive orientation
+                        conn.append(ids)
+        self.conn = np.array(conn)
+        self.gp_elem = np.arange(len(self.conn))
+        B, wdet = [], []
+        for nodes in self.conn:
+            J = X[nodes].T @ _DN_TET                 # J_ij = sum_a X_a,i dN_a/dxi_j
+            B.append(_DN_TET @ np.linalg.inv(J))
+            wdet.append(np.linalg.det(J) / 6.0)      # one point, weight 1/6 of the unit tetrahedron
+        self.B = np.array(B)                         # (ngp, 4, 3)
+        self.wdet = np.array(wdet)
+        self.ngp = len(self.B)
+        self.mass = np.zeros(self.nnodes)
+        np.add.at(self.mass, self.conn.ravel(), np.repeat(rho0 * self.wdet / 4.0, 4))
+        self.volume = self.wdet.sum()
 
 
 class ExplicitBar:

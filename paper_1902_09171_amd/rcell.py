@@ -24,7 +24,7 @@ EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev",
            "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
            "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
            "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps",
-           "rcell_qr_dev", "rcell_stress_return_dev", "rcell_minimize"]
+           "rcell_qr_dev", "rcell_stress_return_dev", "rcell_minimize", "rcell_probe_peaks"]
 
 
 class RCellError(RuntimeError):
@@ -79,6 +79,7 @@ def load():
             "rcell_prof_enable": [vp, i32], "rcell_prof_read": [vp, i32, vp, vp],
             "rcell_set_graph_steps": [vp, i32],
             "rcell_qr_dev": [vp, i32, vp, vp, vp, vp], "rcell_stress_return_dev": [vp, vp, i32, vp, vp, vp],
+            "rcell_probe_peaks": [ctypes.c_size_t, vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -115,6 +116,15 @@ def qr_dev(F_dev_ptr, n, Q_dev_ptr, R_dev_ptr, status_dev_ptr=None, stream=None)
     st = load().rcell_qr_dev(F_dev_ptr, int(n), Q_dev_ptr, R_dev_ptr, status_dev_ptr, stream)
     if st != OK:
         raise RCellError(st, "qr_dev")
+
+
+def probe_peaks(copy_bytes=1 << 30, stream=None):
+    """Measured copy bandwidth (GB/s, read + write) and FP32 FMA rate (TFLOP/s) of the GPU."""
+    gbs, tf = ctypes.c_double(), ctypes.c_double()
+    st = load().rcell_probe_peaks(int(copy_bytes), ctypes.byref(gbs), ctypes.byref(tf), stream)
+    if st != OK:
+        raise RCellError(st, "rcell_probe_peaks failed")
+    return gbs.value, tf.value
 
 
 def stress_return_dev(F_dev_ptr, sigma_md_dev_ptr, n, sigma_fem_dev_ptr, P_dev_ptr=None, stream=None):

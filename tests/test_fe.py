@@ -1,14 +1,21 @@
-"""Pins for the host FE driver (Eqs. 10-14): the patch test, internal forces as the exact
-gradient of the discrete strain energy, lumped mass, and the closed-form uniaxial response of a
-neo-Hookean bar reached quasi-statically by the explicit solver."""
+"""Pins for the host FE driver (Eqs. 10-14), for both meshes (hex8 bricks, C3D4 tetrahedra): the
+patch test, internal forces as the exact gradient of the discrete strain energy, lumped mass, the
+conformity of the tetrahedral mesh, and the closed-form uniaxial response of a neo-Hookean bar
+reached quasi-statically by the explicit solver."""
+from collections import Counter
+
 import numpy as np
 import pytest
 
 from paper_1902_09171_amd import fe
 
 
-def test_patch_test_homogeneous_motion():
-    m = fe.Hex8Bar(nel=(4, 2, 2), size=(40.0, 10.0, 12.0), imperfection=0.9)
+MESHES = [fe.Hex8Bar, fe.Tet4Bar]
+
+
+@pytest.mark.parametrize("mesh", MESHES)
+def test_patch_test_homogeneous_motion(mesh):
+    m = mesh(nel=(4, 2, 2), size=(40.0, 10.0, 12.0), imperfection=0.9)
     F0 = np.array([[1.1, 0.05, -0.02], [0.01, 0.95, 0.03], [0.0, -0.04, 1.02]])
     u = m.X @ (F0 - np.eye(3)).T
     F = m.deformation_gradients(u)
@@ -22,8 +29,9 @@ def test_patch_test_homogeneous_motion():
     assert np.abs(f.sum(0)).max() < 1e-11
 
 
-def test_internal_force_is_energy_gradient():
-    m = fe.Hex8Bar(nel=(2, 1, 1), size=(4.0, 2.0, 2.0), imperfection=0.9)
+@pytest.mark.parametrize("mesh", MESHES)
+def test_internal_force_is_energy_gradient(mesh):
+    m = mesh(nel=(2, 1, 1), size=(4.0, 2.0, 2.0), imperfection=0.9)
     mat = fe.neo_hookean(1.3, 2.1)
     rng = np.random.default_rng(0)
     u = 0.05 * rng.standard_normal((m.nnodes, 3))
@@ -38,9 +46,10 @@ def test_internal_force_is_energy_gradient():
             assert (W(up) - W(um)) / (2 * h) == pytest.approx(f[a, i], rel=1e-6, abs=1e-9)
 
 
-def test_quasistatic_uniaxial_neo_hookean():
+@pytest.mark.parametrize("mesh", MESHES)
+def test_quasistatic_uniaxial_neo_hookean(mesh):
     mu, lam = 1.0, 1.5
-    m = fe.Hex8Bar(nel=(4, 1, 1), size=(8.0, 2.0, 2.0), rho0=1.0)
+    m = mesh(nel=(4, 1, 1), size=(8.0, 2.0, 2.0), rho0=1.0)
     mat = fe.neo_hookean(mu, lam)
     strain, steps = 0.02, 4000
     dt = 0.02
@@ -64,3 +73,20 @@ def test_quasistatic_uniaxial_neo_hookean():
     reaction = -m.internal_forces(mat(F)[0])[bar.right, 0].sum()
     assert -reaction == pytest.approx(Pxx * 2.0 * 2.0, rel=2e-3)
     assert fe.tensile_stress(bar.history[-1]["sigma"]) == pytest.approx(Pxx * lam1 / (lam1 * lt * lt), rel=2e-2)
+
+
+def test_tetrahedral_mesh_is_conforming():
+    """The paper's specimen: 100 C3D4 elements filling the cube, every interior face shared by
+    exactly two elements and the surface covered by two triangles per brick face."""
+    m = fe.Tet4Bar(nel=(5, 2, 2), size=(22.7, 22.7, 22.7))
+    assert m.ngp == 100 and m.conn.shape == (100, 4)
+    assert np.all(m.wdet > 0)
+    assert m.volume == pytest.approx(22.7 ** 3, rel=1e-13)
+    faces = Counter(tuple(sorted(np.delete(t, q))) for t in m.conn for q in range(4))
+    assert set(faces.values()) == {1, 2}
+    assert sum(1 for v in faces.values() if v == 1) == 2 * 2 * (5 * 2 + 5 * 2 + 2 * 2)
+    # a uniaxial homogeneous stress: the pulled face carries P_xx times its area
+    P = np.zeros((m.ngp, 3, 3))
+    P[:, 0, 0] = 1.7
+    f = m.internal_forces(P)
+    assert f[m.face(0, 1), 0].sum() == pytest.approx(1.7 * 22.7 * 22.7, rel=1e-12)
