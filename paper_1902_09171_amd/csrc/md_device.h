@@ -1204,21 +1204,22 @@ __global__ __launch_bounds__(TILE) void k_reset_order(MDArgs a, int first, int c
 }
 
 // Verlet list of every atom (after the reorder, so positions are in bin order): cell-local j with
-// |d| < rc + skin over the 27 (distinct) neighbour bins.  LPA lanes share one atom; lane l scans
-// bins l, l + LPA, ..., each a contiguous range of positions, and keeps its first STASH accepted
-// neighbours in LDS while counting all of them.  An exclusive scan over the lanes gives each lane's
-// offset; the stashed entries are then written out, and only an atom with a lane that accepted
-// more than STASH scans its bins a second time, writing directly.  The list order (lane-major over
-// bins, ascending position inside a bin) is deterministic either way.  A block covers BUILD_ATOMS
-// atoms, so TILE / BUILD_ATOMS blocks cover one tile.
+// |d| < rc + skin over the 27 (distinct) neighbour bins.  Because the atoms are stored in bin order
+// and bins are numbered with z fastest, the three z-neighbour bins of each (x, y) column of the
+// stencil are one contiguous range of positions (two at the periodic edge in z): at most 18 ranges
+// per atom, which the atom's LPA lanes look up once into LDS.  The lanes then walk the concatenated
+// candidates interleaved - lane l takes candidates l, l + LPA, ... - so a group of lanes reads
+// consecutive positions and every lane has the same share of the work whatever the bin sizes.
+// The list is written in candidate order in the same pass (a ballot per candidate slot gives each
+// accepted candidate its index), so it is deterministic.  A block covers BUILD_ATOMS atoms, so
+// TILE / BUILD_ATOMS blocks cover one tile.
 constexpr int LPA = 8;
 constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
-constexpr int STASH = 8;
+constexpr int MAX_RANGES = 18;   // 3 x 3 columns, each at most two ranges
 template <class P, class LT>
 __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
   constexpr int PER_TILE = TILE / BUILD_ATOMS;
-  constexpr int NT = BUILD_ATOMS * LPA;
-  __shared__ int stash[STASH * NT];          // entry e of thread t at stash[e * NT + t]
+  __shared__ int2 rng[BUILD_ATOMS][MAX_RANGES];   // candidate ranges (first position, count) per atom
   const int tb = block_tile(a.ntiles, blockIdx.x / PER_TILE);
   if (tb >= a.ntiles) return;
   const Tile t = a.tiles[tb];
@@ -1247,66 +1248,77 @@ __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
       lst[q][0] = 0; lst[q][1] = 1; lst[q][2] = 2;
     }
   }
-  const bool full = cnt[0] == 3 && cnt[1] == 3 && cnt[2] == 3;
-  const int nq = cnt[0] * cnt[1] * cnt[2];
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
   const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
-  // visit this lane's neighbours in list order
-  auto scan_bins = [&](auto&& take) {
-    for (int q = lane; q < nq && active; q += LPA) {
-      int u0, u1, u2;
-      if (full) {                               // division by constants
-        u0 = q / 9; u1 = (q / 3) % 3; u2 = q % 3;
-      } else {
-        u0 = q / (cnt[1] * cnt[2]); u1 = (q / cnt[2]) % cnt[1]; u2 = q % cnt[2];
+  // z part of every column: bins [z0, z1], or [z0, z1] and [z2, z2] at the periodic edge
+  const int nbz = C.nb[2];
+  int zr[2][2] = {{0, nbz - 1}, {0, 0}}, nzr = 1;
+  if (nbz >= 3) {
+    if (bb[2] == 0) { zr[0][0] = 0; zr[0][1] = 1; zr[1][0] = zr[1][1] = nbz - 1; nzr = 2; }
+    else if (bb[2] == nbz - 1) { zr[0][0] = nbz - 2; zr[0][1] = nbz - 1; zr[1][0] = zr[1][1] = 0; nzr = 2; }
+    else { zr[0][0] = bb[2] - 1; zr[0][1] = bb[2] + 1; }
+  }
+  const int nrange = cnt[0] * cnt[1] * nzr;
+  int2* rg = rng[threadIdx.x / LPA];
+  for (int r = lane; r < nrange; r += LPA) {
+    const int col = r / nzr, part = r - col * nzr;
+    const int u0 = col / cnt[1], u1 = col - u0 * cnt[1];
+    const int bc = C.bin_off + (lst[0][u0] * C.nb[1] + lst[1][u1]) * nbz;
+    const int bf = bc + zr[part][0], bl = bc + zr[part][1];
+    const int beg = a.bstart[bf];
+    rg[r] = make_int2(beg, a.bstart[bl] + a.bnum[bl] - beg);
+  }
+  __syncthreads();
+  // Walk this lane's candidates, UNR in flight.  For each candidate slot the atom's lanes take a
+  // ballot of the accepted ones and write them at the running count plus the accepted lanes below
+  // them, so the list comes out in candidate order (neighbours that sit next to each other in
+  // memory are next to each other in the list) in a single pass.
+  const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
+  const unsigned gshift = (threadIdx.x & 63u) & ~(unsigned)(LPA - 1), below = (1u << lane) - 1u;
+  int count = 0;
+  if (active && nrange > 0) {
+    int r = 0, off = 0;                       // range r holds candidates [off, off + cur.y)
+    int2 cur = rg[0];
+    for (int c0 = lane;; c0 += UNR * LPA) {
+      int pos[UNR];
+      bool ok[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int c = c0 + u * LPA;
+        while (r < nrange && c >= off + cur.y) {
+          off += cur.y;
+          if (++r < nrange) cur = rg[r];
+        }
+        ok[u] = r < nrange;
+        pos[u] = ok[u] ? cur.x + (c - off) : li;
       }
-      const int b = (lst[0][u0] * C.nb[1] + lst[1][u1]) * C.nb[2] + lst[2][u2];
-      // the atoms are in bin order: bin b holds the consecutive positions bstart .. bstart + m - 1
-      const int p0 = a.bstart[C.bin_off + b];
-      const int m = a.bnum[C.bin_off + b];
-      for (int e0 = 0; e0 < m; e0 += UNR) {     // UNR candidates in flight
-        typename P::S sj[UNR];
+      if (!ok[0]) break;
+      typename P::S sj[UNR];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, p0 + min(e0 + u, m - 1));
+      for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, pos[u]);
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int lj = p0 + e0 + u;
-          if (e0 + u >= m || lj == li) continue;
+      for (int u = 0; u < UNR; ++u) {
+        bool acc = false;
+        if (ok[u] && pos[u] != li) {
           typename P::R d[3];
           P::sep(sj[u], si, g, d);
-          if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) take(lj);
+          acc = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2;
         }
+        const unsigned gm = (unsigned)(__ballot(acc) >> gshift) & ((1u << LPA) - 1u);
+        if (acc) {
+          const int k = count + __popc(gm & below);
+          if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii)] = (LT)pos[u];
+        }
+        count += __popc(gm);
       }
+      if (!ok[UNR - 1]) break;
     }
-  };
-  int mine = 0;
-  scan_bins([&](int lj) {
-    if (mine < STASH) stash[mine * NT + threadIdx.x] = lj;
-    ++mine;
-  });
-  int incl = mine;                            // inclusive scan over the LPA lanes of the atom
-#pragma unroll
-  for (int o = 1; o < LPA; o <<= 1) {
-    const int v = __shfl_up(incl, o, LPA);
-    if (lane >= o) incl += v;
   }
-  const int base = incl - mine;
-  int n = __shfl(incl, LPA - 1, LPA);         // total for the atom
-  int over = mine > STASH ? 1 : 0;            // does any lane of the atom need a second scan
+  // the atom's total: its lanes stop counting when their own candidates end, so take the largest
+  int n = count;
 #pragma unroll
-  for (int o = 1; o < LPA; o <<= 1) over |= __shfl_xor(over, o, LPA);
-  const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
-  if (!over) {
-    for (int e = 0; e < mine; ++e)
-      if (base + e < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)(base + e), np, ii)] = (LT)stash[e * NT + threadIdx.x];
-  } else {
-    int k = base;
-    scan_bins([&](int lj) {
-      if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii)] = (LT)lj;
-      ++k;
-    });
-  }
+  for (int o = 1; o < LPA; o <<= 1) n = max(n, __shfl_xor(n, o, LPA));
   if (active && lane == 0) {
     if (n > a.maxnb) {
       atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
