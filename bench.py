@@ -26,6 +26,9 @@ Workloads (``--workload``; every run prints one JSON line):
               a step is one FE load step with 500 MD steps.
   fe_scaling  the system of the paper's scaling test on one GPU: 1000 C3D4 tetrahedra = 1000 r-cells
               of 100 x 100 beads (10^7 beads); a step is one FE load step with 100 MD steps.
+  glassy_rates  direct MD of glassy cells at the constant strain rates 0.01, 0.015, 0.02 / tau of
+              the paper's direct-MD comparison (a new F before every MD step), beside the r-cell's
+              load-step protocol at the same mean rates; a step is one MD step.
   surrogate   the stress surrogate network (153 -> 4 x 256 -> 6, ensemble of 5, BF16 matrix cores
               with FP32 accumulation): ensemble evaluations per second at the bar's batch (256
               Gauss points) and at a large batch, and training samples per second.
@@ -67,7 +70,8 @@ BYTES_PER_BEAD_STEP = 104
 ORACLE_SECONDS = 10.0     # CPU time the oracle baseline runs for (bounded sample of the workload)
 DEFAULTS = {"cu_element": (50, 3), "cu_batched": (10, 2), "kg_single": (1000, 100), "kg_batched": (10, 1),
             "kg_glassy": (10, 1),
-            "fe_bar": (4, 1), "fe_tet": (4, 1), "fe_scaling": (3, 1), "surrogate": (200, 20)}
+            "fe_bar": (4, 1), "fe_tet": (4, 1), "fe_scaling": (3, 1), "glassy_rates": (4000, 100),
+            "surrogate": (200, 20)}
 
 
 def kernel_source_hash():
@@ -318,7 +322,7 @@ def _fe_tet_cell(c):
 
 def _fe_scaling_cell(c):
     from synth import configs
-    return configs.fe_tet_cells(cells_subset=[c], stream=6)["cells"][0]
+    return configs.fe_tet_cells(cells_subset=[c], stream=8)["cells"][0]
 
 
 def _kg_glassy_cell(c):
@@ -387,6 +391,86 @@ def bench_kg_batched(args, torch, rcell, configs, glassy=False):
 
 def bench_kg_glassy(args, torch, rcell, configs):
     return bench_kg_batched(args, torch, rcell, configs, glassy=True)
+
+
+def bench_glassy_rates(args, torch, rcell, configs):
+    """Direct MD under a constant engineering strain rate (a new isochoric uniaxial F before every
+    MD step) at the three rates of the paper's direct-MD comparison (Fig. 6a), next to the r-cell
+    protocol at the same mean rates (the strain of a 100-step load step applied at once, then the
+    window-averaged stress): one glassy cell of 100 x 100 beads per rate, same initial state."""
+    import numpy as np
+    from synth import uniaxial_isochoric
+    RATES, N = (0.01, 0.015, 0.02), 100
+    cfg = configs.kg_glassy(ncells=1)
+    params, cell0 = cfg["params"], cfg["cells"][0]
+    cells = [dict(cell0) for _ in RATES]
+    natoms = len(cell0["x"]) * len(RATES)
+    dt = params["dt"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    A = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)      # continuous
+    B = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)      # load steps
+    lanes = A.set_lanes(args.lanes)
+    B.set_lanes(lanes)
+    nst = args.steps - args.steps % N
+    F_cont = np.stack([np.stack([uniaxial_isochoric(r * dt * (t + 1)) for r in RATES]) for t in range(nst)])
+    F_load = np.stack([np.stack([uniaxial_isochoric(r * dt * N * (k + 1)) for r in RATES]) for k in range(nst // N)])
+    F_cont_dev = torch.tensor(F_cont, dtype=torch.float64, device=dev)
+    F_load_dev = torch.tensor(F_load, dtype=torch.float64, device=dev)
+    sig_a = torch.zeros((nst, len(RATES), 6), dtype=torch.float64, device=dev)
+    sig_b = torch.zeros((nst // N, len(RATES), 6), dtype=torch.float64, device=dev)
+    for g in (A, B):                                  # untimed equilibration at F = I
+        g.run(args.warmup)
+        g.get_stress()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(nst):
+        A.set_deformation_dev(F_cont_dev[t].data_ptr())
+        A.run(1)
+        A.get_stress_dev(sig_a[t].data_ptr(), None)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    for k in range(nst // N):
+        B.set_deformation_dev(F_load_dev[k].data_ptr())
+        B.run(N)
+        B.get_stress_dev(sig_b[k].data_ptr(), None)
+    torch.cuda.synchronize()
+    elapsed_b = time.perf_counter() - t1
+    (avg_s, n), _ = kernel_avg(A, 0, lambda: A.run(100))
+    check_status(A)
+    check_status(B)
+    sa, sb = sig_a.cpu().numpy(), sig_b.cpu().numpy()
+    tens = lambda s: s[..., 0] - 0.5 * (s[..., 1] + s[..., 2])       # uniaxial along x, tension +
+    wa = tens(sa).reshape(nst // N, N, len(RATES)).mean(1)              # continuous, per load-step window
+    wb = tens(sb)
+    curves = {}
+    for c, r in enumerate(RATES):
+        rows = []
+        for eps in (0.05, 0.1, 0.15, 0.2):
+            k = int(round(eps / (r * dt * N))) - 1
+            if 0 <= k < nst // N:
+                rows.append([round(r * dt * N * (k + 1), 4), float(wa[k, c]), float(wb[k, c])])
+        curves[str(r)] = rows
+    achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM, "traffic": None, "kernel": "k_force_kg", "avg_us": avg_s * 1e6,
+                "launches": n, "note": "a new F before every MD step: bound by the deformation's latency"}
+    out = md_line(args, "glassy_rates", natoms * nst / elapsed, elapsed, natoms,
+                  {"description": "direct MD at constant engineering strain rates 0.01, 0.015, 0.02 / tau (new "
+                                  "isochoric uniaxial F before every MD step), one glassy Kremer-Grest cell of "
+                                  "100 x 100 beads per rate (LJ to 2.5 sigma, T = 0.1, dt 0.005)",
+                   "cells": len(RATES), "atoms": natoms, "md_steps_per_step": 1, "lanes_per_atom": lanes},
+                  roofline,
+                  extra={"load_step_path_atom_steps_per_s": natoms * nst / elapsed_b,
+                         "tensile_stress_curves": {"columns": ["strain", "direct MD (mean over the load step's "
+                                                               "window)", "r-cell load steps of 100 MD steps"],
+                                                   "by_rate": curves}})
+    if not args.no_cpu_baseline:
+        F1 = np.stack([uniaxial_isochoric(0.01)])
+        cb, _ = oracle_sample(params, [cell0], F1, 20, "one of the glassy cells")
+        out["cpu_baseline"] = cb
+    return out
 
 
 # The FE workloads: mesh, r-cell generator, MD steps per load step and the text of the line.
@@ -529,7 +613,8 @@ def bench_surrogate(args, torch, rcell, configs):
 WORKLOADS = {"cu_element": bench_cu_element, "cu_batched": bench_cu_batched, "kg_single": bench_kg_single,
              "kg_batched": bench_kg_batched, "kg_glassy": bench_kg_glassy,
              "fe_bar": lambda *a: bench_fe(*a, name="fe_bar"), "fe_tet": lambda *a: bench_fe(*a, name="fe_tet"),
-             "fe_scaling": lambda *a: bench_fe(*a, name="fe_scaling"), "surrogate": bench_surrogate}
+             "fe_scaling": lambda *a: bench_fe(*a, name="fe_scaling"), "glassy_rates": bench_glassy_rates,
+             "surrogate": bench_surrogate}
 
 
 def main():

@@ -881,14 +881,15 @@ __global__ void k_fire_iters(const CellDev* cells, int ncells, int* iters, int* 
 constexpr int RED_NT = 64;
 __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
   CellDev& C = a.cells[blockIdx.x];
-  if (mode == RED_PRIME && !C.pending) return;
-  if ((mode == RED_STATIC || mode == RED_MOVE) && C.fdone) return;
+  // the parts are summed before the cell's flags are consulted, so that their loads do not wait
+  // for the flags (a cell that is skipped below simply discards its sums)
+  const int ntile = C.ntile, tile_off = C.tile_off;
   double W[6] = {0, 0, 0, 0, 0, 0}, K[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
   long long xi[3] = {0, 0, 0};
   float m = 0.f;
   int st = 0;
-  for (int k = threadIdx.x; k < C.ntile; k += RED_NT) {
-    const Part& p = a.parts[C.tile_off + k];
+  for (int k = threadIdx.x; k < ntile; k += RED_NT) {
+    const Part& p = a.parts[tile_off + k];
 #pragma unroll
     for (int q = 0; q < 6; ++q) { W[q] += p.W[q]; K[q] += p.K[q]; }
     pe += p.pe;
@@ -896,6 +897,8 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
     m = fmaxf(m, p.maxd2);
     st = min(st, p.status);
   }
+  if (mode == RED_PRIME && !C.pending) return;
+  if ((mode == RED_STATIC || mode == RED_MOVE) && C.fdone) return;
   double r[13];
 #pragma unroll
   for (int q = 0; q < 6; ++q) { r[q] = wave_sum(W[q]); r[6 + q] = wave_sum(K[q]); }

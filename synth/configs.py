@@ -134,9 +134,9 @@ def fe_bar_cells(ncells=256, nchains=400, chain_len=100, precision="mixed", cell
     return dict(name="fe_bar", params=kg_params(precision=precision), cells=cells)
 
 
-def fe_tet_cells(ncells=100, nchains=100, chain_len=100, precision="mixed", cells_subset=None, stream=5):
+def fe_tet_cells(ncells=100, nchains=100, chain_len=100, precision="mixed", cells_subset=None, stream=7):
     """r-cells of the paper's polymer specimen (Sec. 3.2): one per C3D4 element, 100 chains of 100
-    beads each (10^4 beads); stream 6 gives the cells of the 1000-element scaling workload."""
+    beads each (10^4 beads); stream 8 gives the cells of the 1000-element scaling workload."""
     idx = range(ncells) if cells_subset is None else cells_subset
     cells = [kg_cell([chain_len] * nchains, cell_seed(MASTER_SEED + stream, c)) for c in idx]
     return dict(name="fe_tet", params=kg_params(precision=precision), cells=cells)
