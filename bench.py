@@ -286,7 +286,7 @@ def bench_kg_single(args, torch, rcell, configs):
                          "us_per_md_step_plain_run": plain_us}, dtype="f64")
     if not args.no_cpu_baseline:
         cb, s_ora = oracle_sample(cfg["params"], cfg["cells"], cfg["F_path"][0], 1000,
-                                  "1000 MD steps of the same cell at the first F")
+                                  "the cell at the first F of the ramp")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cfg["cells"], cfg["F_path"][0],
                                                            1000, s_ora, lanes)
@@ -382,7 +382,7 @@ def bench_kg_batched(args, torch, rcell, configs, glassy=False):
                    "lanes_per_atom": lanes, "rebuilds": g.rebuilds()}, roofline)
     if not args.no_cpu_baseline:
         sub = list(range(16))
-        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F[sub], 20, "the first 16 cells, 20 MD steps")
+        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F[sub], 20, "the first 16 cells of the batch")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F[sub], 20,
                                                            s_ora, lanes)
