@@ -28,7 +28,7 @@ EV_A3_TO_GPA = 160.21766208
 
 def kg_params(**over):
     p = dict(potential="kg", precision="mixed", dt=0.005, temperature=1.0, gamma=0.5, mass=1.0,
-             kB=1.0, mvv2e=1.0, rc=2.0 ** (1.0 / 6.0), skin=0.3, lj_eps=1.0, lj_sigma=1.0,
+             kB=1.0, mvv2e=1.0, rc=2.0 ** (1.0 / 6.0), skin=0.4, lj_eps=1.0, lj_sigma=1.0,
              fene_K=30.0, fene_R0=1.5, sc_eps=0.0, sc_a=0.0, sc_c=0.0, sc_n=0, sc_m=0,
              seed=MASTER_SEED, include_kinetic=1)
     p.update(over)
@@ -38,7 +38,7 @@ def kg_params(**over):
 def cu_params(**over):
     a = 3.615
     p = dict(potential="sc_eam", precision="mixed", dt=1.0, temperature=300.0, gamma=0.01,
-             mass=63.546, kB=KB_EV, mvv2e=MVV2E_METAL_FS, rc=1.95 * a, skin=2.0, lj_eps=0.0,
+             mass=63.546, kB=KB_EV, mvv2e=MVV2E_METAL_FS, rc=1.95 * a, skin=1.75, lj_eps=0.0,
              lj_sigma=0.0, fene_K=0.0, fene_R0=0.0, sc_eps=1.2382e-2, sc_a=a, sc_c=39.432,
              sc_n=9, sc_m=6, seed=MASTER_SEED, include_kinetic=1)
     p.update(over)
