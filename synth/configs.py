@@ -1,4 +1,4 @@
-"""The four synthetic r-cell MD workloads, as plain dictionaries of numpy arrays.
+"""The synthetic r-cell MD workloads, as plain dictionaries of numpy arrays.
 
 Each builder returns {"name", "params", "cells", "F"/"F_path", ...}.  "params" is a dict of the
 MD parameters (the same keys for the GPU library and the oracle); "cells" is a list of
@@ -10,7 +10,10 @@ Workloads (their shapes follow the paper's cells; the states are synthetic, not 
   cu_element  8 FCC copper cells (4000 atoms each) of one hex8 element, Sutton-Chen EAM, 300 K,
               per-cell uniaxial F to 5 % strain followed by a random rotation
   kg_batched  512 KG cells of 2k-20k beads, chain lengths U{50..200}, F = rotation x stretch
+  kg_glassy   100 glassy KG cells (LJ to 2.5 sigma, T = 0.1) of 100 x 100 beads
   fe_bar      256 KG cells x 40 000 beads (400 chains x 100), the r-cells of an 8x2x2 hex8 bar
+  fe_tet      KG cells of 100 x 100 beads, one per C3D4 element (the paper's specimen and its
+              1000-element scaling system)
 """
 import numpy as np
 
@@ -47,8 +50,9 @@ def cu_params(**over):
 
 def kg_glassy_params(**over):
     """Glassy Kremer-Grest: the LJ attraction kept (cut and shifted at 2.5 sigma) at T = 0.1, below
-    the glass transition (~0.35); otherwise the standard parameters."""
-    p = kg_params(rc=2.5, temperature=0.1)
+    the glass transition (~0.35); otherwise the standard parameters.  Skin 0.3 sigma: with ~90
+    neighbours per bead and little motion at T = 0.1 the pair work, not the rebuilds, sets the cost."""
+    p = kg_params(rc=2.5, temperature=0.1, skin=0.3)
     p.update(over)
     return p
 
