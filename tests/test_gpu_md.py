@@ -280,6 +280,7 @@ def test_full_cu_element_parity(rc):
     cfg = configs.cu_element()
     p = cfg["params"]
     g = rc.RCellBatch(p, cfg["cells"])
+    g.set_lanes(0)                       # the benchmark's launch configuration: autotuned lanes
     o = core.OracleBatch(p, cfg["cells"])
     F = cfg["F_path"][3]
     g.set_deformation(F); o.set_deformation(F)
