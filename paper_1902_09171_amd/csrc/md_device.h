@@ -974,13 +974,7 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
 //   k_bin_sort   order every bin by atom index (one thread per bin), so that the neighbour lists
 //                and the force sums built from them are deterministic
 template <class P>
-__global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
-  const int tb = block_tile(a.ntiles, blockIdx.x);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
-  const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  const long long i = (long long)t.begin + threadIdx.x;
+__device__ __forceinline__ void bin_atom(const MDArgs& a, const CellDev& C, long long i) {
   double x = a.x[i], y = a.y[i], z = a.z[i];
   const double s0 = C.Hi[0] * x + C.Hi[1] * y + C.Hi[2] * z, s1 = C.Hi[4] * y + C.Hi[5] * z, s2 = C.Hi[8] * z;
   const double k0 = floor(s0), k1 = floor(s1), k2 = floor(s2);
@@ -1003,11 +997,19 @@ __global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
   atomicAdd(&a.bcount[C.bin_off + bin], 1);
 }
 
+template <class P>
+__global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  bin_atom<P>(a, C, (long long)t.begin + threadIdx.x);
+}
+
 constexpr int SCAN_NT = 1024;
-__global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
-  __shared__ int sh[SCAN_NT];
-  CellDev& C = a.cells[blockIdx.x];
-  if (!C.rebuild) return;
+// exclusive scan of one cell's histogram by a block of SCAN_NT threads (sh: SCAN_NT ints of LDS)
+__device__ __forceinline__ void scan_cell(const MDArgs& a, CellDev& C, int* sh) {
   const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
   const int t = threadIdx.x;
   if (t == 0) {                    // the list about to be built holds every pair within rc + skin
@@ -1038,17 +1040,27 @@ __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
   }
 }
 
+__global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
+  __shared__ int sh[SCAN_NT];
+  CellDev& C = a.cells[blockIdx.x];
+  if (!C.rebuild) return;
+  scan_cell(a, C, sh);
+}
+
+__device__ __forceinline__ void fill_atom(const MDArgs& a, const CellDev& C, long long i) {
+  const int pk = a.abin[i];
+  const int bin = ((pk & BIN_MASK) * C.nb[1] + ((pk >> BIN_BITS) & BIN_MASK)) * C.nb[2] + (pk >> (2 * BIN_BITS));
+  const int slot = atomicAdd(&a.bfill[C.bin_off + bin], 1);
+  a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
+}
+
 __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
   const int tb = block_tile(a.ntiles, blockIdx.x);
   if (tb >= a.ntiles) return;
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  const long long i = (long long)t.begin + threadIdx.x;
-  const int pk = a.abin[i];
-  const int bin = ((pk & BIN_MASK) * C.nb[1] + ((pk >> BIN_BITS) & BIN_MASK)) * C.nb[2] + (pk >> (2 * BIN_BITS));
-  const int slot = atomicAdd(&a.bfill[C.bin_off + bin], 1);
-  a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
+  fill_atom(a, C, (long long)t.begin + threadIdx.x);
 }
 
 // one lane per bin slot of every cell (grid over the bin capacity), one wave per block.  Each bin
@@ -1148,13 +1160,7 @@ struct Reorder {
 };
 
 template <class P>
-__global__ __launch_bounds__(TILE) void k_reorder_gather(MDArgs a) {
-  const int tb = block_tile(a.ntiles, blockIdx.x);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
-  const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  const long long q = (long long)t.begin + threadIdx.x;
+__device__ __forceinline__ void reorder_gather_atom(const MDArgs& a, const CellDev& C, long long q) {
   const long long src = C.off + a.binned[q];
   const Reorder<P> r(a);
   r.x[q] = a.x[src]; r.y[q] = a.y[src]; r.z[q] = a.z[src];
@@ -1167,13 +1173,17 @@ __global__ __launch_bounds__(TILE) void k_reorder_gather(MDArgs a) {
 }
 
 template <class P>
-__global__ __launch_bounds__(TILE) void k_reorder_scatter(MDArgs a) {
+__global__ __launch_bounds__(TILE) void k_reorder_gather(MDArgs a) {
   const int tb = block_tile(a.ntiles, blockIdx.x);
   if (tb >= a.ntiles) return;
   const Tile t = a.tiles[tb];
   const CellDev& C = a.cells[t.cell];
   if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  const long long q = (long long)t.begin + threadIdx.x;
+  reorder_gather_atom<P>(a, C, (long long)t.begin + threadIdx.x);
+}
+
+template <class P>
+__device__ __forceinline__ void reorder_scatter_atom(const MDArgs& a, const CellDev& C, long long q) {
   const Reorder<P> r(a);
   a.x[q] = r.x[q]; a.y[q] = r.y[q]; a.z[q] = r.z[q];
   a.vx[q] = r.vx[q]; a.vy[q] = r.vy[q]; a.vz[q] = r.vz[q];
@@ -1190,6 +1200,52 @@ __global__ __launch_bounds__(TILE) void k_reorder_scatter(MDArgs a) {
   b.z = b0.z < 0 ? -1 : a.pos_of[C.off + b0.z];
   b.w = b0.w < 0 ? -1 : a.pos_of[C.off + b0.w];
   a.bond[q] = b;
+}
+
+template <class P>
+__global__ __launch_bounds__(TILE) void k_reorder_scatter(MDArgs a) {
+  const int tb = block_tile(a.ntiles, blockIdx.x);
+  if (tb >= a.ntiles) return;
+  const Tile t = a.tiles[tb];
+  const CellDev& C = a.cells[t.cell];
+  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
+  reorder_scatter_atom<P>(a, C, (long long)t.begin + threadIdx.x);
+}
+
+// The six preparation phases of a rebuild (bin, scan, fill, sort, reorder gather and scatter) for
+// cells of at most PREP_ATOMS atoms: one block per cell runs them in turn, separated by block
+// barriers, so a step in which no cell rebuilds costs one launch instead of six.  Same results as
+// the phase kernels: the bins are ordered by original index (keys staged in LDS, each bin
+// rank-sorted by one thread; keys are distinct), so the reorder depends only on positions.
+constexpr int PREP_ATOMS = 4096;
+template <class P>
+__global__ __launch_bounds__(SCAN_NT) void k_cell_prep(MDArgs a) {
+  __shared__ int sh[SCAN_NT];
+  __shared__ int key[PREP_ATOMS];
+  CellDev& C = a.cells[blockIdx.x];
+  if (!C.rebuild) return;
+  const int n = C.n, t = threadIdx.x;
+  for (int l = t; l < n; l += SCAN_NT) bin_atom<P>(a, C, (long long)C.off + l);
+  __syncthreads();
+  scan_cell(a, C, sh);                       // ends with a barrier
+  for (int l = t; l < n; l += SCAN_NT) fill_atom(a, C, (long long)C.off + l);
+  __syncthreads();
+  for (int q = t; q < n; q += SCAN_NT) key[q] = a.gid[C.off + a.binned[C.off + q]];
+  __syncthreads();
+  const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
+  for (int b = t; b < nbins; b += SCAN_NT) {
+    const int p0 = a.bstart[C.bin_off + b], m = a.bnum[C.bin_off + b];
+    for (int e = 0; e < m; ++e) {
+      const int v = key[p0 + e];
+      int rank = 0;
+      for (int q = 0; q < m; ++q) rank += key[p0 + q] < v;
+      a.binned[C.off + p0 + rank] = a.pos_of[C.off + v];
+    }
+  }
+  __syncthreads();
+  for (int q = t; q < n; q += SCAN_NT) reorder_gather_atom<P>(a, C, (long long)C.off + q);
+  __syncthreads();
+  for (int q = t; q < n; q += SCAN_NT) reorder_scatter_atom<P>(a, C, (long long)C.off + q);
 }
 
 // Original order for the atoms of cells [first, first + count) (create, set_state): gid and

@@ -50,6 +50,8 @@ struct rcell_ctx {
   char* pscr = nullptr;           // reorder scratch rows
   void* nbr = nullptr;
   bool list16 = false;            // 16-bit list entries (every cell has at most 65536 atoms, mixed)
+  bool small_cells = false;       // every cell has at most PREP_ATOMS atoms
+  bool cell_prep = false;         // rebuild preparation by one block per cell (k_cell_prep)
   int *nn = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr, *sort_tmp = nullptr;
   int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
   CellDev* cells = nullptr;
@@ -293,18 +295,23 @@ void launch_reduce(rcell_ctx* c, int mode) {
 void launch_build(rcell_ctx* c) {
   const MDArgs a = make_args(c);
   const dim3 gt(tile_grid(c->ntiles)), bt(TILE), gc(c->ncells), bc(SCAN_NT);
-  if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gt, bt, 0, c->stream, a);
-  else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
-  hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
-  hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
-  hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64),
-                     sizeof(int) * c->sort_cap, c->stream, a, (const int*)c->bin_cell, c->sort_cap);
-  if (c->fp64) {
-    hipLaunchKernelGGL(k_reorder_gather<FP64>, gt, bt, 0, c->stream, a);
-    hipLaunchKernelGGL(k_reorder_scatter<FP64>, gt, bt, 0, c->stream, a);
+  if (c->cell_prep) {              // small cells: the six preparation phases in one launch
+    if (c->fp64) hipLaunchKernelGGL(k_cell_prep<FP64>, gc, bc, 0, c->stream, a);
+    else hipLaunchKernelGGL(k_cell_prep<Mixed>, gc, bc, 0, c->stream, a);
   } else {
-    hipLaunchKernelGGL(k_reorder_gather<Mixed>, gt, bt, 0, c->stream, a);
-    hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gt, bt, 0, c->stream, a);
+    if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gt, bt, 0, c->stream, a);
+    else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
+    hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
+    hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
+    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64),
+                       sizeof(int) * c->sort_cap, c->stream, a, (const int*)c->bin_cell, c->sort_cap);
+    if (c->fp64) {
+      hipLaunchKernelGGL(k_reorder_gather<FP64>, gt, bt, 0, c->stream, a);
+      hipLaunchKernelGGL(k_reorder_scatter<FP64>, gt, bt, 0, c->stream, a);
+    } else {
+      hipLaunchKernelGGL(k_reorder_gather<Mixed>, gt, bt, 0, c->stream, a);
+      hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gt, bt, 0, c->stream, a);
+    }
   }
   const dim3 gl(tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)), bl(BUILD_ATOMS * LPA);
   if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a);
@@ -540,6 +547,8 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
   c->N = N;
   c->npad = (N + 63) / 64 * 64;
   c->list16 = !c->fp64 && *std::max_element(c->n.begin(), c->n.end()) <= 65536;
+  c->small_cells = *std::max_element(c->n.begin(), c->n.end()) <= PREP_ATOMS;
+  c->cell_prep = c->small_cells;
   c->ntiles = ntiles;
   c->occ.assign(ncells, 0.0);
   for (int k = 0; k < ncells; ++k) set_occupancy(c, k, (double)cells[k].natoms / bins_exact(cells[k].H0, rcs));
@@ -919,6 +928,16 @@ int rcell_set_graph_steps(rcell_ctx* c, int32_t steps) {
   if (!c || steps < 0 || (steps & 1)) return c ? fail(c, RCELL_ERR_ARG, "graph steps must be even and >= 0") : RCELL_ERR_ARG;
   drop_graphs(c);
   c->graph_steps = steps;
+  return RCELL_OK;
+}
+
+int rcell_set_build_mode(rcell_ctx* c, int32_t mode) {
+  if (!c || mode < 0 || mode > 2) return c ? fail(c, RCELL_ERR_ARG, "build mode must be 0, 1 or 2") : RCELL_ERR_ARG;
+  if (mode == 1 && !c->small_cells)
+    return fail(c, RCELL_ERR_ARG, "one block per cell needs every cell to have at most " +
+                                      std::to_string(PREP_ATOMS) + " atoms");
+  drop_graphs(c);
+  c->cell_prep = mode == 0 ? c->small_cells : mode == 1;
   return RCELL_OK;
 }
 

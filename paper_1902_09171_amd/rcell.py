@@ -24,7 +24,8 @@ EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev",
            "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
            "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
            "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps",
-           "rcell_qr_dev", "rcell_stress_return_dev", "rcell_minimize", "rcell_probe_peaks"]
+           "rcell_qr_dev", "rcell_stress_return_dev", "rcell_minimize", "rcell_probe_peaks",
+           "rcell_set_build_mode"]
 
 
 class RCellError(RuntimeError):
@@ -75,7 +76,7 @@ def load():
             "rcell_get_forces": [vp, i32, vp], "rcell_get_state": [vp, i32, vp, vp, vp, vp, vp],
             "rcell_set_state": [vp, i32, vp, vp, vp, vp, i64], "rcell_get_energy": [vp, vp, vp],
             "rcell_get_box": [vp, i32, vp, vp, vp, vp], "rcell_get_rebuilds": [vp, vp],
-            "rcell_set_lanes": [vp, i32], "rcell_get_lanes": [vp, vp],
+            "rcell_set_lanes": [vp, i32], "rcell_get_lanes": [vp, vp], "rcell_set_build_mode": [vp, i32],
             "rcell_prof_enable": [vp, i32], "rcell_prof_read": [vp, i32, vp, vp],
             "rcell_set_graph_steps": [vp, i32],
             "rcell_qr_dev": [vp, i32, vp, vp, vp, vp], "rcell_stress_return_dev": [vp, vp, i32, vp, vp, vp],
@@ -251,6 +252,10 @@ class RCellBatch:
     def set_lanes(self, lanes):
         self._check(load().rcell_set_lanes(self._h, int(lanes)))
         return self.lanes()
+
+    def set_build_mode(self, mode):
+        """0: automatic, 1: one block per cell for the rebuild preparation, 2: phase kernels."""
+        self._check(load().rcell_set_build_mode(self._h, int(mode)))
 
     def set_graph_steps(self, steps):
         self._check(load().rcell_set_graph_steps(self._h, int(steps)))

@@ -330,6 +330,32 @@ def test_small_deformations_keep_the_list_exact(rc):
     assert g.rebuilds() - n0 < 2 * nload
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rebuild_preparation_paths_are_bitwise_equal(rc, prec):
+    # one block per cell (the default for small cells) and the six phase kernels order the bins and
+    # the atoms identically, so the lists, forces and trajectories are the same bit for bit
+    cells = kg_cells([[50] * 20, [30] * 30, [40] * 40], seed0=400)
+    p = configs.kg_params(precision=prec)
+    F = np.stack([configs.uniaxial_isochoric(0.02 * (k + 1)) for k in range(3)])
+    res = []
+    for mode in (1, 2):
+        g = rc.RCellBatch(p, cells)
+        g.set_build_mode(mode)
+        g.set_deformation(F)
+        g.run(200)
+        res.append((g.get_stress(), [g.get_state(k)["x"] for k in range(3)], g.rebuilds(), g.status()))
+    (s1, x1, r1, st1), (s2, x2, r2, st2) = res
+    print("rebuilds", r1, r2, flush=True)
+    assert r1 > 0 and r1 == r2
+    assert np.array_equal(s1, s2)
+    assert all(np.array_equal(a, b) for a, b in zip(x1, x2))
+    assert np.all(st1 == 0) and np.all(st2 == 0)
+    with pytest.raises(rc.RCellError):
+        rc.RCellBatch(p, kg_cells([[100] * 50], seed0=500)).set_build_mode(1)   # 5000 beads
+    with pytest.raises(rc.RCellError):
+        g.set_build_mode(3)
+
+
 @pytest.mark.parametrize("pot", ["kg", "cu"])
 def test_graph_replay_equals_eager_launches(rc, pot):
     # replays of the captured MD-step graphs (with neighbour rebuilds inside) give bit-identical
