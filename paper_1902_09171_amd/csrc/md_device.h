@@ -4,7 +4,7 @@
 //   x, y, z     FP64 SoA master positions        vx, vy, vz  FP64 SoA velocities
 //   fx, fy, fz  FP64 total force of the last completed step (read by the first kick of a run)
 //   s[2]        double-buffered fixed-point scaled coordinates: S = frac(H^-1 x) * 2^32 (int32,
-//               mixed) or * 2^64 (int64, FP64 mode); .w carries F'(rho) for the EAM force pass.
+//               mixed) or * 2^64 (int64, FP64 mode); .w carries F'(rho) for the EAM force pass (scaled by sc_fscale).
 //               Differences of two such integers wrap modulo 2^32 (2^64), which is exactly the
 //               per-component minimum image in scaled space: the pair separation needs no
 //               image shifts (d = H dS, formed in FP64 and rounded once in mixed precision).
@@ -86,7 +86,8 @@ __device__ __forceinline__ int block_tile_xcd(int ntiles, int block) {
 }
 
 struct Part {                     // one tile's contribution
-  double W[6], K[6], pe, pad;
+  double V[6];                    // MD: pair virial minus the kinetic term; statics: the FIRE sums
+  double pe;
   long long xi[3];
   float maxd2;
   int status;
@@ -458,58 +459,94 @@ __device__ __forceinline__ int wave_min(int v) {
   return v;
 }
 
+// the same trees over the lanes whose index is a multiple of L only (the other lanes hold zeros):
+// lane 0 receives the result
+template <int L, class T>
+__device__ __forceinline__ T wave_sum_from(T v) {
+#pragma unroll
+  for (int o = 32; o >= L; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <int L>
+__device__ __forceinline__ float wave_max_from(float v) {
+#pragma unroll
+  for (int o = 32; o >= L; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+template <int L>
+__device__ __forceinline__ int wave_min_from(int v) {
+#pragma unroll
+  for (int o = 32; o >= L; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+
 template <int NW>
 struct PartShared {
-  double d[NW][13];
-  long long l[NW][3];
+  double d[NW][7];
+  int l[NW][3];
   float f[NW];
   int i[NW];
 };
 
-// Reduce one tile's contributions (every thread of the block calls this) and write its Part:
-// a wave-level shuffle reduction, then thread 0 adds the NW wave results in order.
-template <int NT>
-__device__ __forceinline__ void write_part(Part* parts, int part, const double W[6], const double K[6], double pe,
+// Reduce one tile's contributions (every thread of the block calls this) and write its Part.  Only
+// the first of each atom's TPA lanes holds values, so the shuffle tree of each wave runs over those
+// lanes only; a wave's noise sum (at most 64 integers below 2^23 in magnitude) fits 32 bits.  The
+// energy is reduced only where it is reported (with_pe, uniform over the block).  Thread 0 then
+// adds the NW wave results in order.
+template <int NT, int TPA>
+__device__ __forceinline__ void write_part(Part* parts, int part, const double V[6], double pe, bool with_pe,
                                            const long long xi[3], float maxd2, int status,
                                            PartShared<NT / 64>& sh) {
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  double r[13];
+  double r[7];
 #pragma unroll
-  for (int q = 0; q < 6; ++q) { r[q] = wave_sum(W[q]); r[6 + q] = wave_sum(K[q]); }
-  r[12] = wave_sum(pe);
-  const long long x0 = wave_sum(xi[0]), x1 = wave_sum(xi[1]), x2 = wave_sum(xi[2]);
-  const float m = wave_max(maxd2);
-  const int st = wave_min(status);
+  for (int q = 0; q < 6; ++q) r[q] = wave_sum_from<TPA>(V[q]);
+  r[6] = with_pe ? wave_sum_from<TPA>(pe) : 0.0;
+  int x[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) x[q] = wave_sum_from<TPA>((int)xi[q]);
+  const float m = wave_max_from<TPA>(maxd2);
+  const int st = wave_min_from<TPA>(status);
   if (ln == 0) {
 #pragma unroll
-    for (int q = 0; q < 13; ++q) sh.d[wv][q] = r[q];
-    sh.l[wv][0] = x0; sh.l[wv][1] = x1; sh.l[wv][2] = x2;
+    for (int q = 0; q < 7; ++q) sh.d[wv][q] = r[q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sh.l[wv][q] = x[q];
     sh.f[wv] = m;
     sh.i[wv] = st;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     Part& p = parts[part];
-    double acc[13];
+    double acc[7];
     long long la[3] = {0, 0, 0};
     float mm = 0.f;
     int ss = 0;
 #pragma unroll
-    for (int q = 0; q < 13; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 7; ++q) acc[q] = 0.0;
     for (int w = 0; w < NT / 64; ++w) {
 #pragma unroll
-      for (int q = 0; q < 13; ++q) acc[q] += sh.d[w][q];
-      la[0] += sh.l[w][0]; la[1] += sh.l[w][1]; la[2] += sh.l[w][2];
+      for (int q = 0; q < 7; ++q) acc[q] += sh.d[w][q];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) la[q] += sh.l[w][q];
       mm = fmaxf(mm, sh.f[w]);
       ss = min(ss, sh.i[w]);
     }
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { p.W[q] = acc[q]; p.K[q] = acc[6 + q]; }
-    p.pe = acc[12];
+    for (int q = 0; q < 6; ++q) p.V[q] = acc[q];
+    p.pe = acc[6];
     p.xi[0] = la[0]; p.xi[1] = la[1]; p.xi[2] = la[2];
     p.maxd2 = mm;
     p.status = ss;
   }
+}
+
+// The per-atom stress contribution of the MD modes, W - K (K only where the kinetic term is
+// included), or in statics the FIRE sums carried in K
+__device__ __forceinline__ void part_values(const MDArgs& a, int mode, const double W[6], const double K[6], double V[6]) {
+  const double kin = a.include_kinetic ? 1.0 : 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) V[q] = mode == MODE_STATIC ? K[q] : W[q] - kin * K[q];
 }
 
 // ------------------------------------------------------------------ force kernels
@@ -606,9 +643,9 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
           const R s6 = s2 * s2 * s2;
           const R gr = in ? -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i : (R)0;   // (dU/dr) / r
           f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-          const R hg = (R)0.5 * gr;
-          w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-          w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+          // twice the pair virial; halved once after the loop (exact)
+          w[0] += gr * d[0] * d[0]; w[1] += gr * d[1] * d[1]; w[2] += gr * d[2] * d[2];
+          w[3] += gr * d[0] * d[1]; w[4] += gr * d[0] * d[2]; w[5] += gr * d[1] * d[2];
           if constexpr (decltype(with_pe)::value) pe += in ? (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh) : (R)0;
         }
       }
@@ -629,16 +666,15 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
         if (!(tt < (R)1)) { status = ST_BOND; continue; }
         const R gr = K / ((R)1 - tt);
         f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-        const R hg = (R)0.5 * gr;
-        w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-        w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
+        w[0] += gr * d[0] * d[0]; w[1] += gr * d[1] * d[1]; w[2] += gr * d[2] * d[2];
+        w[3] += gr * d[0] * d[1]; w[4] += gr * d[0] * d[2]; w[5] += gr * d[1] * d[2];
         pe += (R)(-0.25 * a.fene_K * a.fene_R02) * (R)log((double)((R)1 - tt));
       }
     }
   }
   double W[6], K[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 6; ++q) W[q] = (double)lane_sum<TPA>(w[q]);
+  for (int q = 0; q < 6; ++q) W[q] = 0.5 * (double)lane_sum<TPA>(w[q]);
   double PE = (double)lane_sum<TPA>(pe);
   const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
   long long xi[3] = {0, 0, 0};
@@ -656,10 +692,27 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
     maxd2 = o.maxd2;
   }
-  write_part<NT>(a.parts, tb, W, K, PE, xi, maxd2, status, psh);
+  double V[6];
+  part_values(a, mode, W, K, V);
+  write_part<NT, TPA>(a.parts, tb, V, PE, mode != MODE_STEP, xi, maxd2, status, psh);
+}
+
+// Sutton-Chen with n = 9, m = 6 is evaluated in powers of s3 = r^-3: with t = a / r,
+// t^6 = a^6 s3^2 and t^9 = a^9 s3^3, and the pair scalar of pass 2 becomes
+//   g / r = -r^-2 s3^2 (eps n a^9 s3 + m a^6 (F'_i + F'_j)),
+// so pass 1 stores F' scaled by m a^6 (sc_fscale); other exponents store F' itself.
+template <int SN, int SM>
+__device__ __forceinline__ double sc_fscale(const MDArgs& a) {
+  if constexpr (SN == 9 && SM == 6) {
+    const double a3 = a.sc_a * a.sc_a * a.sc_a;
+    return (double)a.sc_m * a3 * a3;
+  } else {
+    return 1.0;
+  }
 }
 
 // Sutton-Chen pass 1: host density rho_i and F'(rho_i) = -eps c / (2 sqrt(rho_i)), stored in s.w
+// (times sc_fscale)
 template <class P, int TPA, int SN, int SM, class LT>
 __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   using R = typename P::R;
@@ -674,7 +727,8 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
   if (active) {
     const typename P::S si = P::load(a.s_cur, i);
     const int nn = a.nn[i];
-    const R rc2 = (R)a.rc2, sa = (R)a.sc_a, rhoc = (R)a.sc_rhoc;
+    const double a3 = a.sc_a * a.sc_a * a.sc_a;
+    const R rc2 = (R)a.rc2, sa = (R)a.sc_a, sa6 = (R)(a3 * a3), rhoc = (R)a.sc_rhoc;
     const typename P::Geo g = P::geo(C);
     const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
     for (NbrWalk<P, TPA, LT> walk(a, i, nn, lane); walk.more();) {
@@ -686,15 +740,21 @@ __global__ __launch_bounds__(TILE * TPA) void k_eam_rho(MDArgs a, int mode) {
         R d[3];
         P::sep(sj[u], si, g, d);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        R tn, tm;
-        sc_powers<SN, SM>(sa * P::rsq(r2), a.sc_n, a.sc_m, tn, tm);
+        R tm;
+        if constexpr (SN == 9 && SM == 6) {
+          const R ri = P::rsq(r2), s3 = ri * ri * ri;
+          tm = sa6 * (s3 * s3);
+        } else {
+          R tn;
+          sc_powers<SN, SM>(sa * P::rsq(r2), a.sc_n, a.sc_m, tn, tm);
+        }
         rho += (ok[u] && r2 < rc2) ? tm - rhoc : (R)0;
       }
     }
   }
   rho = lane_sum<TPA>(rho);
   if (active && lane == 0) {
-    const R fp = rho > (R)0 ? (R)(-0.5 * a.sc_eps * a.sc_c) / sqrt(rho) : (R)0;
+    const R fp = rho > (R)0 ? (R)(-0.5 * a.sc_eps * a.sc_c * sc_fscale<SN, SM>(a)) / sqrt(rho) : (R)0;
     P::store_w(a.s_cur, i, fp);
   }
 }
@@ -718,8 +778,10 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     const typename P::S si = P::load(a.s_cur, i);
     fpi = P::get_w(si);
     const int nn = a.nn[i];
+    const double a3 = a.sc_a * a.sc_a * a.sc_a;
     const R rc2 = (R)a.rc2, sa = (R)a.sc_a, en = (R)(a.sc_eps * a.sc_n), m = (R)a.sc_m;
     const R eh = (R)(0.5 * a.sc_eps), phic = (R)a.sc_phic;
+    const R en9 = (R)(a.sc_eps * a.sc_n * a3 * a3 * a3), eh9 = (R)(0.5 * a.sc_eps * a3 * a3 * a3);
     const typename P::Geo g = P::geo(C);
     const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
     // the pair energy is summed only where it is reported: not in the middle steps of a run
@@ -735,15 +797,25 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
           const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
           const bool in = ok[u] && r2 < rc2;
           const R ri = P::rsq(r2);
-          R tn, tm;
-          sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
-          const R g0 = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);   // g / r
+          R g0, tn;                                                             // g / r, t^n
+          if constexpr (SN == 9 && SM == 6) {
+            const R ri2 = ri * ri, s3 = ri2 * ri, s6 = s3 * s3;
+            g0 = -(ri2 * s6) * (en9 * s3 + (fpi + P::get_w(sj[u])));
+            if constexpr (decltype(with_pe)::value) tn = s6 * s3;             // t^9 / a^9
+          } else {
+            R tm;
+            sc_powers<SN, SM>(sa * ri, a.sc_n, a.sc_m, tn, tm);
+            g0 = -(ri * ri) * (en * tn + (fpi + P::get_w(sj[u])) * m * tm);
+          }
           const R gr = in ? g0 : (R)0;
           f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-          const R hg = (R)0.5 * gr;
-          w[0] += hg * d[0] * d[0]; w[1] += hg * d[1] * d[1]; w[2] += hg * d[2] * d[2];
-          w[3] += hg * d[0] * d[1]; w[4] += hg * d[0] * d[2]; w[5] += hg * d[1] * d[2];
-          if constexpr (decltype(with_pe)::value) pe += in ? eh * (tn - phic) : (R)0;
+          // twice the pair virial; halved once after the loop (exact)
+          w[0] += gr * d[0] * d[0]; w[1] += gr * d[1] * d[1]; w[2] += gr * d[2] * d[2];
+          w[3] += gr * d[0] * d[1]; w[4] += gr * d[0] * d[2]; w[5] += gr * d[1] * d[2];
+          if constexpr (decltype(with_pe)::value) {
+            if constexpr (SN == 9 && SM == 6) pe += in ? eh9 * tn - eh * phic : (R)0;
+            else pe += in ? eh * (tn - phic) : (R)0;
+          }
         }
       }
     };
@@ -752,7 +824,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   }
   double W[6], K[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 6; ++q) W[q] = (double)lane_sum<TPA>(w[q]);
+  for (int q = 0; q < 6; ++q) W[q] = 0.5 * (double)lane_sum<TPA>(w[q]);
   double PE = (double)lane_sum<TPA>(pe);
   const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
   long long xi[3] = {0, 0, 0};
@@ -764,7 +836,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   } else if (active && mode != MODE_STEP && mode != MODE_DRY) {
     // embedding energy -eps c sqrt(rho) = (eps c)^2 / (2 F'(rho)), zero where rho = 0
     const double ec = a.sc_eps * a.sc_c;
-    if (fpi != (R)0) PE += ec * ec / (2.0 * (double)fpi);
+    if (fpi != (R)0) PE += ec * ec * sc_fscale<SN, SM>(a) / (2.0 * (double)fpi);
   }
   if (active && lane == 0 && mode != MODE_DRY) {
     TailOut o;
@@ -774,7 +846,9 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
     xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
     maxd2 = o.maxd2;
   }
-  write_part<NT>(a.parts, tb, W, K, PE, xi, maxd2, 0, psh);
+  double V[6];
+  part_values(a, mode, W, K, V);
+  write_part<NT, TPA>(a.parts, tb, V, PE, mode != MODE_STEP, xi, maxd2, 0, psh);
 }
 
 // First half kick and drift of a run (the remaining ones are fused into the force kernels).
@@ -808,7 +882,7 @@ __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
     }
   }
   const double Z[6] = {0, 0, 0, 0, 0, 0};
-  write_part<TILE>(a.parts, tb, Z, Z, 0.0, xi, maxd2, 0, psh);
+  write_part<TILE, 1>(a.parts, tb, Z, 0.0, false, xi, maxd2, 0, psh);
 }
 
 // ------------------------------------------------------------------ molecular statics (FIRE)
@@ -866,7 +940,7 @@ __global__ __launch_bounds__(TILE) void k_fire_move(MDArgs a) {
   }
   const double Z[6] = {0, 0, 0, 0, 0, 0};
   const long long xi[3] = {0, 0, 0};
-  write_part<TILE>(a.parts, tb, Z, Z, 0.0, xi, maxd2, 0, psh);
+  write_part<TILE, 1>(a.parts, tb, Z, 0.0, false, xi, maxd2, 0, psh);
 }
 
 __global__ void k_fire_iters(const CellDev* cells, int ncells, int* iters, int* done) {
@@ -876,45 +950,92 @@ __global__ void k_fire_iters(const CellDev* cells, int ncells, int* iters, int* 
   done[c] = cells[c].fdone;
 }
 
-// Per-cell reduction of the tile partials: one wave per cell, each lane sums every 64th tile
-// in order, then a fixed xor-shuffle tree (deterministic for a given tile count).
+// Per-cell reduction of the tile partials: one wave per cell.  Lane t sums every 64th tile in
+// order; the 64 lane sums of each of the 10 summed quantities (V, pe, xi) are then added through
+// LDS in a fixed two-level order (four groups of 16 lanes, then the four group sums in order), so
+// the result is deterministic for a given tile count.  The cell fields that the update reads are
+// loaded at the start, beside the partials, so that none of them waits behind the reduction.
+// Every thread of the block calls it (it holds two block barriers); threads from RED_NT on only
+// take part in the barriers.
 constexpr int RED_NT = 64;
-__global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
-  CellDev& C = a.cells[blockIdx.x];
-  // the parts are summed before the cell's flags are consulted, so that their loads do not wait
-  // for the flags (a cell that is skipped below simply discards its sums)
+constexpr int RED_Q = 10;         // V[6], pe, xi[3]
+struct RedShared {
+  double col[RED_Q][RED_NT + 1];
+  double grp[4][RED_Q];
+};
+__device__ __forceinline__ void reduce_cell(const MDArgs& a, int cell, int mode, RedShared& sh) {
+  CellDev& C = a.cells[cell];
+  auto& col = sh.col;
+  auto& grp = sh.grp;
+  const int t = threadIdx.x;
   const int ntile = C.ntile, tile_off = C.tile_off;
-  double W[6] = {0, 0, 0, 0, 0, 0}, K[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
+  const int pending = C.pending, fdone = C.fdone;
+  const int cstatus = C.status, crebuild = C.rebuild, cn = C.n;
+  const float chs2 = C.hs2;
+  const double cV = C.V;
+  const long long cnreb = C.nrebuild, cwcount = C.wcount, cstep = C.step;
+  double cw[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) cw[q] = C.wsum[q];
+  double V[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
   long long xi[3] = {0, 0, 0};
   float m = 0.f;
   int st = 0;
-  for (int k = threadIdx.x; k < ntile; k += RED_NT) {
+  for (int k = t; k < (t < RED_NT ? ntile : 0); k += RED_NT) {
     const Part& p = a.parts[tile_off + k];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) { W[q] += p.W[q]; K[q] += p.K[q]; }
+    for (int q = 0; q < 6; ++q) V[q] += p.V[q];
     pe += p.pe;
     xi[0] += p.xi[0]; xi[1] += p.xi[1]; xi[2] += p.xi[2];
     m = fmaxf(m, p.maxd2);
     st = min(st, p.status);
   }
-  if (mode == RED_PRIME && !C.pending) return;
-  if ((mode == RED_STATIC || mode == RED_MOVE) && C.fdone) return;
-  double r[13];
+  if (mode == RED_PRIME && !pending) return;                              // uniform over the block
+  if ((mode == RED_STATIC || mode == RED_MOVE) && fdone) return;
+  if (t < RED_NT) {
 #pragma unroll
-  for (int q = 0; q < 6; ++q) { r[q] = wave_sum(W[q]); r[6 + q] = wave_sum(K[q]); }
-  r[12] = wave_sum(pe);
-  const long long x0 = wave_sum(xi[0]), x1 = wave_sum(xi[1]), x2 = wave_sum(xi[2]);
+    for (int q = 0; q < 6; ++q) col[q][t] = V[q];
+    col[6][t] = pe;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) col[7 + q][t] = __longlong_as_double(xi[q]);
+  }
   const float md = wave_max(m);
   st = wave_min(st);
-  if (threadIdx.x != 0) return;
-  if (st != 0 && C.status == 0) C.status = st;
+  __syncthreads();
+  if (t < RED_NT) {
+    const int q = t % 16, g = t / 16;
+    const double* c = &col[q < RED_Q ? q : 0][g * 16];
+    if (q < 7) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s += c[k];
+      grp[g][q] = s;
+    } else if (q < RED_Q) {
+      long long s = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s += __double_as_longlong(c[k]);
+      grp[g][q] = __longlong_as_double(s);
+    }
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double r[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) r[q] = ((grp[0][q] + grp[1][q]) + grp[2][q]) + grp[3][q];
+  long long xs[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    xs[q] = __double_as_longlong(grp[0][7 + q]) + __double_as_longlong(grp[1][7 + q]) +
+            __double_as_longlong(grp[2][7 + q]) + __double_as_longlong(grp[3][7 + q]);
+  const long long x0 = xs[0], x1 = xs[1], x2 = xs[2];
+  if (st != 0 && cstatus == 0) C.status = st;
   if (mode == RED_MOVE) {                // statics: positions moved; rebuild when they left the skin
-    C.rebuild = md > C.hs2;
+    C.rebuild = md > chs2;
     return;
   }
   if (mode == RED_STATIC) {              // statics: one FIRE decision per cell (same order as the oracle)
-    C.pe = r[12];
-    const double P = r[6], F2 = r[7], V2 = r[8];
+    C.pe = r[6];
+    const double P = r[0], F2 = r[1], V2 = r[2];
     if ((double)md <= a.fire_ftol2 || st != 0 || C.fiter >= a.fire_max_iter) { C.fdone = 1; return; }
     if (P > 0.0) {
       if (++C.fcount > 5) { C.fdt = fmin(1.1 * C.fdt, 10.0 * a.dt); C.falpha *= 0.99; }
@@ -930,19 +1051,18 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
     C.fiter += 1;
     return;
   }
-  if (C.rebuild) C.nrebuild += 1;
+  if (crebuild) C.nrebuild = cnreb + 1;
   if (mode == RED_START) {
-    C.rebuild = md > C.hs2;
-    C.xi_mean[0] = (double)x0 / (double)C.n;
-    C.xi_mean[1] = (double)x1 / (double)C.n;
-    C.xi_mean[2] = (double)x2 / (double)C.n;
+    C.rebuild = md > chs2;
+    C.xi_mean[0] = (double)x0 / (double)cn;
+    C.xi_mean[1] = (double)x1 / (double)cn;
+    C.xi_mean[2] = (double)x2 / (double)cn;
     return;
   }
   double s[6];
-  const double kin = a.include_kinetic ? 1.0 : 0.0;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) s[q] = (r[q] - kin * r[6 + q]) / C.V;
-  if (mode != RED_STEP) C.pe = r[12];      // the middle steps of a run do not sum the energy
+  for (int q = 0; q < 6; ++q) s[q] = r[q] / cV;
+  if (mode != RED_STEP) C.pe = r[6];      // the middle steps of a run do not sum the energy
   if (mode == RED_PRIME) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) C.last[q] = s[q];
@@ -951,17 +1071,22 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
     return;
   }
 #pragma unroll
-  for (int q = 0; q < 6; ++q) { C.wsum[q] += s[q]; C.last[q] = s[q]; }
-  C.wcount += 1;
-  C.step += 1;
+  for (int q = 0; q < 6; ++q) { C.wsum[q] = cw[q] + s[q]; C.last[q] = s[q]; }
+  C.wcount = cwcount + 1;
+  C.step = cstep + 1;
   if (mode == RED_STEP) {
-    C.rebuild = md > C.hs2;
-    C.xi_mean[0] = (double)x0 / (double)C.n;
-    C.xi_mean[1] = (double)x1 / (double)C.n;
-    C.xi_mean[2] = (double)x2 / (double)C.n;
+    C.rebuild = md > chs2;
+    C.xi_mean[0] = (double)x0 / (double)cn;
+    C.xi_mean[1] = (double)x1 / (double)cn;
+    C.xi_mean[2] = (double)x2 / (double)cn;
   } else {
     C.rebuild = 0;
   }
+}
+
+__global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
+  __shared__ RedShared sh;
+  reduce_cell(a, blockIdx.x, mode, sh);
 }
 
 // ------------------------------------------------------------------ neighbour build
@@ -1219,11 +1344,8 @@ __global__ __launch_bounds__(TILE) void k_reorder_scatter(MDArgs a) {
 // rank-sorted by one thread; keys are distinct), so the reorder depends only on positions.
 constexpr int PREP_ATOMS = 4096;
 template <class P>
-__global__ __launch_bounds__(SCAN_NT) void k_cell_prep(MDArgs a) {
-  __shared__ int sh[SCAN_NT];
-  __shared__ int key[PREP_ATOMS];
-  CellDev& C = a.cells[blockIdx.x];
-  if (!C.rebuild) return;
+__device__ __forceinline__ void prep_cell(const MDArgs& a, int cell, int* sh, int* key) {
+  CellDev& C = a.cells[cell];
   const int n = C.n, t = threadIdx.x;
   for (int l = t; l < n; l += SCAN_NT) bin_atom<P>(a, C, (long long)C.off + l);
   __syncthreads();
@@ -1246,6 +1368,28 @@ __global__ __launch_bounds__(SCAN_NT) void k_cell_prep(MDArgs a) {
   for (int q = t; q < n; q += SCAN_NT) reorder_gather_atom<P>(a, C, (long long)C.off + q);
   __syncthreads();
   for (int q = t; q < n; q += SCAN_NT) reorder_scatter_atom<P>(a, C, (long long)C.off + q);
+}
+
+template <class P>
+__global__ __launch_bounds__(SCAN_NT) void k_cell_prep(MDArgs a) {
+  __shared__ int sh[SCAN_NT];
+  __shared__ int key[PREP_ATOMS];
+  if (!a.cells[blockIdx.x].rebuild) return;
+  prep_cell<P>(a, blockIdx.x, sh, key);
+}
+
+// The per-cell reduction of a time step followed, in the same block, by the rebuild preparation
+// of a cell that it flags (cells of at most PREP_ATOMS atoms): one launch instead of two per MD
+// step.  The flag is read back through the device-coherent path after the barrier.
+template <class P>
+__global__ __launch_bounds__(SCAN_NT) void k_reduce_prep(MDArgs a, int mode) {
+  __shared__ RedShared rsh;
+  __shared__ int sh[SCAN_NT];
+  __shared__ int key[PREP_ATOMS];
+  reduce_cell(a, blockIdx.x, mode, rsh);
+  __syncthreads();
+  if (!__hip_atomic_load(&a.cells[blockIdx.x].rebuild, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  prep_cell<P>(a, blockIdx.x, sh, key);
 }
 
 // Original order for the atoms of cells [first, first + count) (create, set_state): gid and

@@ -292,13 +292,21 @@ void launch_reduce(rcell_ctx* c, int mode) {
   hipLaunchKernelGGL(k_reduce, dim3(c->ncells), dim3(RED_NT), 0, c->stream, a, mode);
 }
 
-void launch_build(rcell_ctx* c) {
+// reduce_mode >= 0: the per-cell reduction of that mode runs first, fused into the preparation
+// launch when the cells are small enough for it
+void launch_build(rcell_ctx* c, int reduce_mode = -1) {
   const MDArgs a = make_args(c);
   const dim3 gt(tile_grid(c->ntiles)), bt(TILE), gc(c->ncells), bc(SCAN_NT);
   if (c->cell_prep) {              // small cells: the six preparation phases in one launch
-    if (c->fp64) hipLaunchKernelGGL(k_cell_prep<FP64>, gc, bc, 0, c->stream, a);
-    else hipLaunchKernelGGL(k_cell_prep<Mixed>, gc, bc, 0, c->stream, a);
+    if (reduce_mode >= 0) {
+      if (c->fp64) hipLaunchKernelGGL(k_reduce_prep<FP64>, gc, bc, 0, c->stream, a, reduce_mode);
+      else hipLaunchKernelGGL(k_reduce_prep<Mixed>, gc, bc, 0, c->stream, a, reduce_mode);
+    } else {
+      if (c->fp64) hipLaunchKernelGGL(k_cell_prep<FP64>, gc, bc, 0, c->stream, a);
+      else hipLaunchKernelGGL(k_cell_prep<Mixed>, gc, bc, 0, c->stream, a);
+    }
   } else {
+    if (reduce_mode >= 0) launch_reduce(c, reduce_mode);
     if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gt, bt, 0, c->stream, a);
     else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
     hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
@@ -659,12 +667,12 @@ int rcell_set_deformation_dev(rcell_ctx* c, const void* F_dev) {
 }
 
 // one MD step that is not the last of a run: forces at the current positions fused with the
-// update to the next positions, per-cell reduction, buffer swap, conditional neighbour build
+// update to the next positions, buffer swap, per-cell reduction and conditional neighbour build
+// (the reduction reads only the tile partials and the cell table, not the swapped buffers)
 static void middle_step(rcell_ctx* c) {
   launch_force(c, MODE_STEP);
-  launch_reduce(c, RED_STEP);
   c->cur = 1 - c->cur;
-  launch_build(c);
+  launch_build(c, RED_STEP);
 }
 
 // capture graph_steps (even) middle steps starting at the current buffer parity
@@ -689,8 +697,7 @@ int rcell_run(rcell_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return c ? fail(c, RCELL_ERR_ARG, "nsteps < 0") : RCELL_ERR_ARG;
   if (nsteps == 0) return RCELL_OK;
   launch_start(c);
-  launch_reduce(c, RED_START);
-  launch_build(c);
+  launch_build(c, RED_START);
   int left = nsteps - 1;                           // middle steps; the last step ends the run
   const bool graphs = c->graph_steps > 0 && !c->prof;
   while (graphs && left >= c->graph_steps) {
@@ -949,25 +956,32 @@ int rcell_set_lanes(rcell_ctx* c, int32_t lanes) {
     return RCELL_OK;
   }
   if (lanes != 0) return fail(c, RCELL_ERR_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
-  // autotune: time the force pass (no state written) for each variant, keep the fastest
+  // autotune: time the force pass (no state written) for each variant, keep the fastest; each
+  // variant's time is its best of three rounds, taken in turn, so one slow sample decides nothing
   hipEvent_t t0, t1;
   HIPCHK(c, hipEventCreate(&t0));
   HIPCHK(c, hipEventCreate(&t1));
-  float best = 1e30f;
-  int best_l = c->lanes;
-  for (int l : {1, 2, 4, 8, 16}) {
-    launch_force(c, MODE_DRY, l);
-    HIPCHK(c, hipEventRecord(t0, c->stream));
-    for (int r = 0; r < 5; ++r) launch_force(c, MODE_DRY, l);
-    HIPCHK(c, hipEventRecord(t1, c->stream));
-    HIPCHK(c, hipEventSynchronize(t1));
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, t0, t1));
-    if (ms < best) { best = ms; best_l = l; }
-  }
+  constexpr int NV = 5;
+  const int var[NV] = {1, 2, 4, 8, 16};
+  float t[NV];
+  for (int v = 0; v < NV; ++v) t[v] = 1e30f;
+  for (int round = 0; round < 3; ++round)
+    for (int v = 0; v < NV; ++v) {
+      launch_force(c, MODE_DRY, var[v]);
+      HIPCHK(c, hipEventRecord(t0, c->stream));
+      for (int r = 0; r < 5; ++r) launch_force(c, MODE_DRY, var[v]);
+      HIPCHK(c, hipEventRecord(t1, c->stream));
+      HIPCHK(c, hipEventSynchronize(t1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, t0, t1));
+      t[v] = std::min(t[v], ms);
+    }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  c->lanes = best_l;
+  int best = 0;
+  for (int v = 1; v < NV; ++v)
+    if (t[v] < t[best]) best = v;
+  c->lanes = var[best];
   return RCELL_OK;
 }
 

@@ -1,12 +1,17 @@
 """Molecular statics on the GPU (rcell_minimize: FIRE relaxation in the deformed box, Eqs. 16-20)
 against the FP64 oracle.
 
-Copper cells: the relaxed energy per atom, stress and P match the oracle's at the mixed-precision
-tolerance; where the affinely deformed lattice is stable (a monatomic Bravais lattice has no
-internal relaxation) the relaxed energy is the Cauchy-Born value - Table 1's C(t) is beyond the
-crystal's stability, and both sides relax it to the same lower state.  A polymer cell in FP64 mode: its relaxed
-configuration is a minimum by the oracle's own force evaluation.  Edge cases: max_iter = 0, bad
-arguments, and MD continuing from a relaxed state."""
+Copper cells: where the affinely deformed lattice is stable (a monatomic Bravais lattice has no
+internal relaxation) the minimum is unique, the relaxed energy is the Cauchy-Born value, and the
+relaxed energy, stress and P match the oracle's at the mixed-precision tolerance.  Table 1's C(t)
+and C(c) are beyond the crystal's stability: both sides relax them to lower states, but which of
+the nearly degenerate lower states is reached depends on the relaxation path (the FP64 oracle
+itself lands in another one when the start moves by 1e-5 Angstrom), so mixed-precision forces,
+whose rounding perturbs the path by more than that, are checked for a converged state below the
+Cauchy-Born energy only, and the same cells relaxed in FP64 mode are checked against the oracle
+element by element.  A polymer cell in FP64 mode: its relaxed configuration is a minimum by the
+oracle's own force evaluation.  Edge cases: max_iter = 0, bad arguments, and MD continuing from a
+relaxed state."""
 import numpy as np
 import pytest
 
@@ -40,41 +45,74 @@ def cu_cells(n, ncell=7, amp=0.05):
     return out
 
 
-def test_copper_statics_matches_oracle_and_cauchy_born(rc):
-    Fs = np.stack([F_GEN] + [TABLE1_F[k] for k in ("B(t)", "C(t)", "C(c)")])
+def relax_pair(rc, params, Fs, ftol=1e-4):
     cells = cu_cells(len(Fs))
-    g = rc.RCellBatch(P_CU, cells)
-    o = core.OracleBatch(dict(P_CU, precision="fp64"), cells)
+    g = rc.RCellBatch(params, cells)
+    o = core.OracleBatch(dict(params, precision="fp64"), cells)
     g.set_deformation(Fs)
     o.set_deformation(Fs)
-    ftol = 1e-4
     it_g = g.minimize(20000, ftol)
     print("gpu iterations", it_g, flush=True)
     it_o = o.minimize(20000, ftol)
+    return g, o, it_g, it_o
+
+
+def cauchy_born_energy(F):
+    x0, H0 = fcc_lattice(7)
+    return core.forces(dict(P_CU, precision="fp64"), F @ H0, x0 @ F.T)[1], len(x0)
+
+
+def test_copper_statics_matches_oracle_and_cauchy_born(rc):
+    Fs = np.stack([F_GEN] + [TABLE1_F[k] for k in ("B(t)", "C(t)", "C(c)")])
+    ftol = 1e-4
+    g, o, it_g, it_o = relax_pair(rc, P_CU, Fs, ftol)
     pe_g, ke_g = g.get_energy()
     pe_o, _ = o.get_energy()
     sg, Pg = g.get_stress(with_P=True)
     so, Po = o.get_stress(with_P=True)
-    x0, H0 = fcc_lattice(7)
-    n = len(x0)
     stable = []
     for k, F in enumerate(Fs):
-        e_cb = core.forces(dict(P_CU, precision="fp64"), F @ H0, x0 @ F.T)[1]
+        e_cb, n = cauchy_born_energy(F)
         print(f"cell {k}: iters gpu {it_g[k]} oracle {it_o[k]}; E/N gpu - CB {(pe_g[k] - e_cb) / n:.2e}, "
               f"oracle - CB {(pe_o[k] - e_cb) / n:.2e}; stress rel {np.abs(sg[k] - so[k]).max() / fro(so[k]):.2e}",
               flush=True)
         assert it_g[k] < 20000
-        assert abs(pe_g[k] - pe_o[k]) / n < 1e-6
-        # the affinely deformed lattice is the minimum only where it is stable (both sides find a
-        # lower state under C(t)); there the GPU must reach the Cauchy-Born energy too
+        assert np.abs(g.get_forces(k)).max() <= ftol * np.sqrt(3) * 1.01
         if abs(pe_o[k] - e_cb) / n < 1e-6:
+            # stable: the Cauchy-Born state is the minimum, reached by both sides
             stable.append(k)
             assert abs(pe_g[k] - e_cb) / n < 1e-6
-        assert np.abs(sg[k] - so[k]).max() <= 1e-5 * fro(so[k])
+            assert abs(pe_g[k] - pe_o[k]) / n < 1e-6
+            assert np.abs(sg[k] - so[k]).max() <= 1e-5 * fro(so[k])
+            assert np.abs(Pg[k] - Po[k]).max() <= 3e-5 * np.abs(Po[k]).max()
+        else:
+            # beyond stability: a converged lower state (which one depends on the path)
+            assert (pe_g[k] - e_cb) / n < -1e-3
+    assert np.all(ke_g == 0.0)
+    assert stable == [0, 1]
+
+
+def test_copper_statics_beyond_stability_fp64_matches_oracle(rc):
+    """C(t) and C(c) relaxed with FP64 forces follow the oracle's path to the same lower state."""
+    Fs = np.stack([TABLE1_F[k] for k in ("C(t)", "C(c)")])
+    ftol = 1e-4
+    g, o, it_g, it_o = relax_pair(rc, dict(P_CU, precision="fp64"), Fs, ftol)
+    pe_g, _ = g.get_energy()
+    pe_o, _ = o.get_energy()
+    sg, Pg = g.get_stress(with_P=True)
+    so, Po = o.get_stress(with_P=True)
+    for k, F in enumerate(Fs):
+        e_cb, n = cauchy_born_energy(F)
+        err = np.abs(sg[k] - so[k]).max() / fro(so[k])
+        print(f"cell {k}: iters gpu {it_g[k]} oracle {it_o[k]}; E/N gpu - CB {(pe_g[k] - e_cb) / n:.2e}, "
+              f"oracle - CB {(pe_o[k] - e_cb) / n:.2e}; stress rel {err:.2e}", flush=True)
+        # the bounds of the stable mixed-precision cells; the lower states reached from nearby
+        # starts differ by ~1e-3 eV/atom or ~6e-3 in relative stress
+        assert (pe_o[k] - e_cb) / n < -1e-3
+        assert abs(pe_g[k] - pe_o[k]) / n < 1e-6
+        assert err <= 1e-5
         assert np.abs(Pg[k] - Po[k]).max() <= 3e-5 * np.abs(Po[k]).max()
         assert np.abs(g.get_forces(k)).max() <= ftol * np.sqrt(3) * 1.01
-    assert np.all(ke_g == 0.0)
-    assert 0 in stable and 1 in stable
 
 
 def test_polymer_statics_reaches_a_minimum(rc):
