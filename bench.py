@@ -212,11 +212,11 @@ def bench_cu_element(args, torch, rcell, configs, ncells=8):
     value = natoms * MD_PER_LOAD * args.steps / elapsed
     flop_launch = FLOP_FORCE_PER_PAIR * PAIRS_PER_ATOM * natoms
     achieved = flop_launch / avg_s
+    name = "cu_element" if ncells == 8 else "cu_batched"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32, "traffic": traffic_from_profiles("k_force_eam", "cu_element"),
+                "frac": achieved / PEAK_FP32, "traffic": traffic_from_profiles("k_force_eam", name),
                 "kernel": "k_force_eam", "avg_us": avg_s * 1e6, "launches": force_n,
                 "density_pass_avg_us": rho_s * 1e6, "flop_per_launch": flop_launch}
-    name = "cu_element" if ncells == 8 else "cu_batched"
     what = ("8 FCC copper r-cells x 4000 atoms (one hex8 element, 2x2x2 Gauss points)" if ncells == 8 else
             f"{ncells} FCC copper r-cells x 4000 atoms (the copper element batched {ncells // 8} times)")
     out = md_line(args, name, value, elapsed, natoms,

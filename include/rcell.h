@@ -155,14 +155,16 @@ int rcell_get_energy(rcell_ctx* ctx, double* pe, double* ke);
 int rcell_get_box(rcell_ctx* ctx, int32_t cell, double* H, double* Q, double* R, double* J);
 /* neighbour-list rebuilds performed so far, summed over cells */
 int rcell_get_rebuilds(rcell_ctx* ctx, int64_t* count);
-/* choose the lanes-per-atom of the force kernels: 0 = autotune by timing each variant on the
- * current state (advances no state), or 1, 2, 4, 8, 16 */
+/* choose the lanes-per-atom of the force kernels: 0 = autotune by timing each variant's MD-step
+ * force pass on copies of the current positions, velocities and forces (advances no state; holds a
+ * temporary device buffer of 72 bytes per atom during the call, RCELL_ERR_OOM if it cannot be
+ * allocated), or 1, 2, 4, 8, 16 */
 int rcell_set_lanes(rcell_ctx* ctx, int32_t lanes);
 /* How a neighbour rebuild prepares its cells (binning, bin order, reordering the atoms by bin):
  * mode 1 runs all of it in one launch with one block per cell (every cell must have at most 4096
  * atoms, else RCELL_ERR_ARG), mode 2 in six launches over all tiles, mode 0 (the default) picks 1
- * when every cell is small enough.  Results are identical either way; mode 1 makes an MD step in
- * which no cell rebuilds five launches shorter. */
+ * when every cell is small enough.  Results are identical either way; mode 1 also runs the per-cell
+ * reduction of each MD step in the same launch, which makes a step six launches shorter. */
 int rcell_set_build_mode(rcell_ctx* ctx, int32_t mode);
 int rcell_get_lanes(rcell_ctx* ctx, int32_t* lanes);
 /* MD steps inside a run are replayed from captured HIP graphs of `steps` steps (even; default

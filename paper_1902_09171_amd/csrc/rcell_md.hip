@@ -279,12 +279,14 @@ void force_p(rcell_ctx* c, const MDArgs& a, int mode, int lanes) {
   }
 }
 
-void launch_force(rcell_ctx* c, int mode, int lanes = -1) {
-  const MDArgs a = make_args(c);
-  const int l = lanes > 0 ? lanes : c->lanes;
+void launch_force_args(rcell_ctx* c, const MDArgs& a, int mode, int l) {
   if (c->fp64) force_p<FP64, int>(c, a, mode, l);
   else if (c->list16) force_p<Mixed, uint16_t>(c, a, mode, l);
   else force_p<Mixed, int>(c, a, mode, l);
+}
+
+void launch_force(rcell_ctx* c, int mode, int lanes = -1) {
+  launch_force_args(c, make_args(c), mode, lanes > 0 ? lanes : c->lanes);
 }
 
 void launch_reduce(rcell_ctx* c, int mode) {
@@ -956,28 +958,48 @@ int rcell_set_lanes(rcell_ctx* c, int32_t lanes) {
     return RCELL_OK;
   }
   if (lanes != 0) return fail(c, RCELL_ERR_ARG, "lanes must be 0, 1, 2, 4, 8 or 16");
-  // autotune: time the force pass (no state written) for each variant, keep the fastest; each
-  // variant's time is its best of three rounds, taken in turn, so one slow sample decides nothing
-  hipEvent_t t0, t1;
-  HIPCHK(c, hipEventCreate(&t0));
-  HIPCHK(c, hipEventCreate(&t1));
+  // autotune: time the MD step's force pass (the pair loops and the integration tail) for each
+  // variant and keep the fastest; each variant's time is its best of three rounds, taken in turn, so
+  // one slow sample decides nothing.  The pass writes positions, velocities and forces, so those
+  // point at copies; the other fixed-point buffer, the tile partials and the EAM F' that it also
+  // writes are rewritten before they are next read.
+  const size_t nb = sizeof(double) * (size_t)c->N;
+  char* tmp = nullptr;
+  if (hipMalloc(&tmp, 9 * nb) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, RCELL_ERR_OOM, "autotune scratch of " + std::to_string(9 * nb) + " bytes");
+  }
+  MDArgs a = make_args(c);
+  double* d[9];
+  for (int k = 0; k < 9; ++k) d[k] = (double*)(tmp + k * nb);
+  const void* src[9] = {c->x, c->y, c->z, c->vx, c->vy, c->vz, c->fx, c->fy, c->fz};
   constexpr int NV = 5;
   const int var[NV] = {1, 2, 4, 8, 16};
   float t[NV];
   for (int v = 0; v < NV; ++v) t[v] = 1e30f;
-  for (int round = 0; round < 3; ++round)
-    for (int v = 0; v < NV; ++v) {
-      launch_force(c, MODE_DRY, var[v]);
-      HIPCHK(c, hipEventRecord(t0, c->stream));
-      for (int r = 0; r < 5; ++r) launch_force(c, MODE_DRY, var[v]);
-      HIPCHK(c, hipEventRecord(t1, c->stream));
-      HIPCHK(c, hipEventSynchronize(t1));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 9 && e == hipSuccess; ++k) e = hipMemcpyAsync(d[k], src[k], nb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  a.x = d[0]; a.y = d[1]; a.z = d[2]; a.vx = d[3]; a.vy = d[4]; a.vz = d[5];
+  a.fx = d[6]; a.fy = d[7]; a.fz = d[8];
+  for (int round = 0; round < 3 && e == hipSuccess; ++round)
+    for (int v = 0; v < NV && e == hipSuccess; ++v) {
+      launch_force_args(c, a, MODE_STEP, var[v]);
+      e = hipEventRecord(t0, c->stream);
+      for (int r = 0; r < 5 && e == hipSuccess; ++r) launch_force_args(c, a, MODE_STEP, var[v]);
+      if (e == hipSuccess) e = hipEventRecord(t1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, t0, t1));
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       t[v] = std::min(t[v], ms);
     }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(c, RCELL_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
   int best = 0;
   for (int v = 1; v < NV; ++v)
     if (t[v] < t[best]) best = v;
