@@ -51,3 +51,19 @@ def test_cpu_baseline_is_the_oracle_on_a_bounded_sample():
     assert cb["kind"] == "oracle" and cb["unit"] == "atom-steps/s" and cb["value"] > 0
     assert cb["cores"] >= 1 and "200 atoms" in cb["sample"]
     assert s.shape == (1, 6) and np.all(np.isfinite(s))
+
+
+def test_traffic_records_belong_to_their_workload_and_source():
+    # a workload without its own counter record reports null traffic, never another workload's
+    assert bench.traffic_from_profiles("k_force_eam", "cu_batched") is None
+    for kernel, w in (("k_force_eam", "cu_element"), ("k_force_kg", "kg_batched"), ("k_force_kg", "fe_tet")):
+        path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{w}.json")
+        got = bench.traffic_from_profiles(kernel, w)
+        if not os.path.exists(path):
+            assert got is None
+            continue
+        rec = json.load(open(path))
+        if rec["source_hash"] == bench.kernel_source_hash():
+            assert got == rec["bytes_per_launch"] and got > 0
+        else:                       # counters taken on other kernel sources are not reported
+            assert got is None
