@@ -55,8 +55,10 @@ def test_cpu_baseline_is_the_oracle_on_a_bounded_sample():
 
 def test_traffic_records_belong_to_their_workload_and_source():
     # a workload without its own counter record reports null traffic, never another workload's
-    assert bench.traffic_from_profiles("k_force_eam", "cu_batched") is None
-    for kernel, w in (("k_force_eam", "cu_element"), ("k_force_kg", "kg_batched"), ("k_force_kg", "fe_tet")):
+    assert not os.path.exists(os.path.join(ROOT, "profiles", "traffic_k_force_kg_kg_glassy.json"))
+    assert bench.traffic_from_profiles("k_force_kg", "kg_glassy") is None
+    for kernel, w in (("k_force_eam", "cu_element"), ("k_force_eam", "cu_batched"), ("k_force_kg", "kg_batched"),
+                      ("k_force_kg", "fe_tet")):
         path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{w}.json")
         got = bench.traffic_from_profiles(kernel, w)
         if not os.path.exists(path):
