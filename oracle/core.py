@@ -199,8 +199,10 @@ class OracleBatch:
                 raise OracleError(st, "set_cell_ids")
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            lib().orc_destroy(self._h)
+        # at interpreter exit the module's globals may already be gone: then the process is ending
+        # and its memory is released with it
+        if getattr(self, "_h", None) and _lib is not None and callable(lib):
+            _lib.orc_destroy(self._h)
             self._h = None
 
     def _check(self, st, what):
