@@ -412,13 +412,14 @@ def bench_glassy_rates(args, torch, rcell, configs):
     B = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)      # load steps
     lanes = A.set_lanes(args.lanes)
     B.set_lanes(lanes)
-    nst = args.steps - args.steps % N
+    nst = args.steps                  # timed MD steps of the direct path, each with its own F
+    nld = max(1, nst // N)            # load steps of N MD steps on the r-cell path
     F_cont = np.stack([np.stack([uniaxial_isochoric(r * dt * (t + 1)) for r in RATES]) for t in range(nst)])
-    F_load = np.stack([np.stack([uniaxial_isochoric(r * dt * N * (k + 1)) for r in RATES]) for k in range(nst // N)])
+    F_load = np.stack([np.stack([uniaxial_isochoric(r * dt * N * (k + 1)) for r in RATES]) for k in range(nld)])
     F_cont_dev = torch.tensor(F_cont, dtype=torch.float64, device=dev)
     F_load_dev = torch.tensor(F_load, dtype=torch.float64, device=dev)
     sig_a = torch.zeros((nst, len(RATES), 6), dtype=torch.float64, device=dev)
-    sig_b = torch.zeros((nst // N, len(RATES), 6), dtype=torch.float64, device=dev)
+    sig_b = torch.zeros((nld, len(RATES), 6), dtype=torch.float64, device=dev)
     for g in (A, B):                                  # untimed equilibration at F = I
         g.run(args.warmup)
         g.get_stress()
@@ -431,7 +432,7 @@ def bench_glassy_rates(args, torch, rcell, configs):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     t1 = time.perf_counter()
-    for k in range(nst // N):
+    for k in range(nld):
         B.set_deformation_dev(F_load_dev[k].data_ptr())
         B.run(N)
         B.get_stress_dev(sig_b[k].data_ptr(), None)
@@ -442,14 +443,15 @@ def bench_glassy_rates(args, torch, rcell, configs):
     check_status(B)
     sa, sb = sig_a.cpu().numpy(), sig_b.cpu().numpy()
     tens = lambda s: s[..., 0] - 0.5 * (s[..., 1] + s[..., 2])       # uniaxial along x, tension +
-    wa = tens(sa).reshape(nst // N, N, len(RATES)).mean(1)              # continuous, per load-step window
+    nwin = nst // N                                                     # whole load-step windows
+    wa = tens(sa[:nwin * N]).reshape(nwin, N, len(RATES)).mean(1)       # continuous, per load-step window
     wb = tens(sb)
     curves = {}
     for c, r in enumerate(RATES):
         rows = []
         for eps in (0.05, 0.1, 0.15, 0.2):
             k = int(round(eps / (r * dt * N))) - 1
-            if 0 <= k < nst // N:
+            if 0 <= k < nwin:
                 rows.append([round(r * dt * N * (k + 1), 4), float(wa[k, c]), float(wb[k, c])])
         curves[str(r)] = rows
     achieved = BYTES_PER_BEAD_STEP * natoms / avg_s
@@ -462,7 +464,7 @@ def bench_glassy_rates(args, torch, rcell, configs):
                                   "100 x 100 beads per rate (LJ to 2.5 sigma, T = 0.1, dt 0.005)",
                    "cells": len(RATES), "atoms": natoms, "md_steps_per_step": 1, "lanes_per_atom": lanes},
                   roofline,
-                  extra={"load_step_path_atom_steps_per_s": natoms * nst / elapsed_b,
+                  extra={"load_step_path_atom_steps_per_s": natoms * nld * N / elapsed_b,
                          "tensile_stress_curves": {"columns": ["strain", "direct MD (mean over the load step's "
                                                                "window)", "r-cell load steps of 100 MD steps"],
                                                    "by_rate": curves}})

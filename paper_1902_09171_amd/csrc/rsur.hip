@@ -341,7 +341,7 @@ int rsur_train_step(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t B
     w.M = c->dp[l]; w.N = c->dp[l + 1]; w.K = Mp;
     w.Z = c->g + c->woff[l]; w.ldz = c->dp[l + 1]; w.sZ = c->P;
     gemm<true, false, EPI_BWD_DW>(c, w);
-    hipLaunchKernelGGL(k_colsum, dim3((c->dp[l + 1] + 63) / 64, c->K), dim3(64), 0, c->stream, dz, sdz, Mp,
+    hipLaunchKernelGGL(k_colsum, dim3((c->dp[l + 1] + 63) / 64, c->K), dim3(64 * COLSUM_RG), 0, c->stream, dz, sdz, Mp,
                        c->dp[l + 1], c->g + c->boff[l], c->P);
     if (l > 0) {                                     // dZ_{l-1} = (dZ_l W_l^T) * SiLU'(Z_{l-1})
       GemmArgs d{};

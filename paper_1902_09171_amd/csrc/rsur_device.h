@@ -227,14 +227,26 @@ __global__ __launch_bounds__(LOSS_NT) void k_loss(const float* out, long long sO
   if (threadIdx.x == 0) loss[mem] = sh[0] * inv;
 }
 
-// bias gradient: column sums of the BF16 output gradient (one thread per member and column)
-__global__ void k_colsum(const bf16* dZ, long long sdZ, int Mp, int ld, float* gb, long long sgb) {
+// bias gradient: column sums of the BF16 output gradient.  A block takes 64 columns of one member
+// with COLSUM_RG row groups (group g sums rows g, g + COLSUM_RG, ...; a wave reads 64 consecutive
+// columns of a row); the group sums meet in LDS and are added in group order (deterministic).
+constexpr int COLSUM_RG = 16;
+__global__ __launch_bounds__(64 * COLSUM_RG) void k_colsum(const bf16* dZ, long long sdZ, int Mp, int ld,
+                                                           float* gb, long long sgb) {
+  __shared__ float part[COLSUM_RG][64];
   const int mem = blockIdx.y;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= ld) return;
+  const int c = threadIdx.x % 64, grp = threadIdx.x / 64;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.0f;
-  for (int m = 0; m < Mp; ++m) s += (float)dZ[mem * sdZ + (long long)m * ld + n];
-  gb[mem * sgb + n] = s;
+  if (n < ld)
+    for (int m = grp; m < Mp; m += COLSUM_RG) s += (float)dZ[mem * sdZ + (long long)m * ld + n];
+  part[grp][c] = s;
+  __syncthreads();
+  if (grp == 0 && n < ld) {
+    float t = 0.0f;
+    for (int g = 0; g < COLSUM_RG; ++g) t += part[g][c];
+    gb[mem * sgb + n] = t;
+  }
 }
 
 // Adam on every padded parameter of every member; refreshes the BF16 copy of the weights
