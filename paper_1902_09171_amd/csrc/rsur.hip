@@ -37,6 +37,8 @@ struct rsur_ctx {
   bf16 *dza = nullptr, *dzb = nullptr;       // K x Mp x max(dp)
   float *xmu = nullptr, *xsd = nullptr, *ymu = nullptr, *ysd = nullptr, *loss = nullptr;
   float *c1 = nullptr, *c2 = nullptr;        // Adam bias corrections per member
+  float* split = nullptr;                    // partial sums of the split gradient reductions
+  float* lpart = nullptr;                    // K x LOSS_CHUNKS partial losses
   std::vector<long long> t;                  // Adam steps per member
   std::vector<void*> allocs;
 };
@@ -70,9 +72,22 @@ int ralloc(rsur_ctx* c, T** out, size_t count) {
 
 int pad64(int v) { return (v + 63) / 64 * 64; }
 
+// The gradient reductions over the batch (weight gradients, bias column sums) are split into S
+// ranges of at least 256 rows (S a power of two up to MAX_SPLIT dividing Mp / 64) so that enough
+// blocks work at once; S partial results are then added in order (deterministic).
+constexpr int MAX_SPLIT = 8;
+int batch_splits(int Mp) {
+  int S = 1;
+  while (S < MAX_SPLIT && (Mp / 64) % (2 * S) == 0 && Mp / (2 * S) >= 256) S *= 2;
+  return S;
+}
+
 template <bool AT, bool BT, int EPI>
 void gemm(rsur_ctx* c, const GemmArgs& a) {
-  hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), dim3(a.N / TN, a.M / TM, c->K), dim3(256), 0, c->stream, a);
+  GemmArgs b = a;
+  b.nmem = c->K;
+  if (b.ksplit < 1) b.ksplit = 1;
+  hipLaunchKernelGGL((k_gemm<AT, BT, EPI>), dim3(b.N / TN, b.M / TM, c->K * b.ksplit), dim3(256), 0, c->stream, b);
 }
 
 // forward of every member for Mp rows already normalised in act[0]; keeps Z and activations
@@ -170,11 +185,16 @@ int rsur_create(int32_t din, int32_t width, int32_t depth, int32_t dout, int32_t
   for (int l = 0; l < c->L - 1; ++l)
     if ((e = ralloc(c, &c->Z[l], (size_t)c->K * c->Mp * c->dp[l + 1]))) return bail(e);
   const int dmax = *std::max_element(c->dp.begin(), c->dp.end());
+  {
+    size_t mn = (size_t)dmax;
+    for (int l = 0; l < c->L; ++l) mn = std::max(mn, (size_t)c->dp[l] * c->dp[l + 1]);
+    if ((e = ralloc(c, &c->split, (size_t)MAX_SPLIT * c->K * mn))) return bail(e);
+  }
   if ((e = ralloc(c, &c->out, (size_t)c->K * c->Mp * c->dp[c->L])) ||
       (e = ralloc(c, &c->dza, (size_t)c->K * c->Mp * dmax)) || (e = ralloc(c, &c->dzb, (size_t)c->K * c->Mp * dmax)) ||
       (e = ralloc(c, &c->xmu, din)) || (e = ralloc(c, &c->xsd, din)) || (e = ralloc(c, &c->ymu, dout)) ||
       (e = ralloc(c, &c->ysd, dout)) || (e = ralloc(c, &c->loss, ensemble)) || (e = ralloc(c, &c->c1, ensemble)) ||
-      (e = ralloc(c, &c->c2, ensemble)))
+      (e = ralloc(c, &c->c2, ensemble)) || (e = ralloc(c, &c->lpart, (size_t)ensemble * LOSS_CHUNKS)))
     return bail(e);
   std::vector<float> zeros(std::max(din, dout), 0.0f), ones(std::max(din, dout), 1.0f);
   if (hipMemsetAsync(c->p, 0, sizeof(float) * KP, c->stream) || hipMemsetAsync(c->g, 0, sizeof(float) * KP, c->stream) ||
@@ -331,8 +351,11 @@ int rsur_train_step(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t B
   const long long sOut = (long long)c->Mp * c->dp[L];
   const int dmax = *std::max_element(c->dp.begin(), c->dp.end());
   const long long sdz = (long long)c->Mp * dmax;
-  hipLaunchKernelGGL(k_loss, dim3(c->K), dim3(LOSS_NT), 0, c->stream, c->out, sOut, c->dp[L], (const float*)Y_dev, B,
-                     c->dout, c->ymu, c->ysd, c->dza, sdz, Mp, c->loss);
+  hipLaunchKernelGGL(k_loss, dim3(LOSS_CHUNKS, c->K), dim3(LOSS_NT), 0, c->stream, c->out, sOut, c->dp[L],
+                     (const float*)Y_dev, B, c->dout, c->ymu, c->ysd, c->dza, sdz, Mp, c->lpart);
+  hipLaunchKernelGGL(k_loss_total, dim3((c->K + 63) / 64), dim3(64), 0, c->stream, c->lpart, c->K, 1.0f / (float)(B * c->dout),
+                     c->loss);
+  const int S = batch_splits(Mp);
   bf16 *dz = c->dza, *dzn = c->dzb;
   for (int l = L - 1; l >= 0; --l) {
     GemmArgs w{};                                    // dW_l = act_l^T dZ_l
@@ -340,9 +363,17 @@ int rsur_train_step(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t B
     w.B = dz; w.ldb = c->dp[l + 1]; w.sB = sdz;
     w.M = c->dp[l]; w.N = c->dp[l + 1]; w.K = Mp;
     w.Z = c->g + c->woff[l]; w.ldz = c->dp[l + 1]; w.sZ = c->P;
+    w.ksplit = S; w.Zs = c->split;
     gemm<true, false, EPI_BWD_DW>(c, w);
-    hipLaunchKernelGGL(k_colsum, dim3((c->dp[l + 1] + 63) / 64, c->K), dim3(64 * COLSUM_RG), 0, c->stream, dz, sdz, Mp,
-                       c->dp[l + 1], c->g + c->boff[l], c->P);
+    const long long nw = (long long)c->K * w.M * w.N, nb = (long long)c->K * c->dp[l + 1];
+    if (S > 1)
+      hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, c->stream, c->split, S, c->K,
+                         w.M, w.N, c->g + c->woff[l], (long long)w.N, c->P);
+    hipLaunchKernelGGL(k_colsum, dim3((c->dp[l + 1] + 63) / 64, c->K, S), dim3(64 * COLSUM_RG), 0, c->stream, dz, sdz,
+                       Mp, c->dp[l + 1], c->g + c->boff[l], c->P, S, c->split);
+    if (S > 1)
+      hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, c->stream, c->split, S, c->K,
+                         1, c->dp[l + 1], c->g + c->boff[l], (long long)c->dp[l + 1], c->P);
     if (l > 0) {                                     // dZ_{l-1} = (dZ_l W_l^T) * SiLU'(Z_{l-1})
       GemmArgs d{};
       d.A = dz; d.lda = c->dp[l + 1]; d.sA = sdz;

@@ -22,6 +22,8 @@ struct GemmArgs {
   float* Z; long long ldz, sZ;             // FP32 result (pre-activation, output or gradient)
   bf16* O; long long ldo, sO;              // BF16 result (activation or backpropagated gradient)
   const float* Zp; long long ldzp, sZp;    // pre-activation whose SiLU derivative scales the result
+  int nmem, ksplit;                        // members; reduction ranges (weight gradient only, else 1)
+  float* Zs;                               // ksplit > 1: partial results [range][member][M][N]
 };
 
 constexpr int TM = 64, TN = 64, TK = 32, LDK = 40;   // tile sizes; LDS row stride padded to 40
@@ -40,7 +42,10 @@ template <bool AT, bool BT, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) bf16 sa[TM * LDK];
   __shared__ __attribute__((aligned(16))) bf16 sb[TN * LDK];
-  const int mem = blockIdx.z;
+  // blockIdx.z = member + nmem * range: the weight gradient's reduction over the batch is split
+  // into ksplit consecutive ranges of K / ksplit (a multiple of TK), each block taking one
+  const int mem = blockIdx.z % g.nmem, ks = blockIdx.z / g.nmem;
+  const int kc = g.K / g.ksplit;
   const bf16* A = g.A + mem * g.sA;
   const bf16* B = g.B + mem * g.sB;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
@@ -49,7 +54,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   v16f acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
+  for (int k0 = ks * kc; k0 < (ks + 1) * kc; k0 += TK) {
     if (!AT) {                                   // 64 rows of 32 contiguous k
       const int r = t >> 2, c = (t & 3) * 8;
       *(v8bf*)&sa[r * LDK + c] = *(const v8bf*)&A[(long long)(m0 + r) * g.lda + k0 + c];
@@ -91,6 +96,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       g.Z[mem * g.sZ + row * g.ldz + col] = v + g.bias[mem * g.sBias + col];
     } else if (EPI == EPI_BWD_DA) {
       g.O[mem * g.sO + row * g.ldo + col] = (bf16)(v * silu_grad(g.Zp[mem * g.sZp + row * g.ldzp + col]));
+    } else if (g.ksplit > 1) {
+      g.Zs[(((long long)ks * g.nmem + mem) * g.M + row) * g.N + col] = v;
     } else {
       g.Z[mem * g.sZ + row * g.ldz + col] = v;
     }
@@ -199,16 +206,20 @@ __global__ void k_norm_in(const float* X, int B, int din, int Mp, int dp0, const
 }
 
 // MSE on normalised outputs per member (one block per member, fixed order) and dLoss/dOutput
-constexpr int LOSS_NT = 1024;
+// Loss and its output gradient: block (chunk, member) takes rows [chunk Mp / LOSS_CHUNKS, ...) of
+// one member and writes its squared-error sum to part[member][chunk] (a fixed tree over the block);
+// k_loss_total adds the chunks in order.  Mp * ldo < 2^31.
+constexpr int LOSS_NT = 256, LOSS_CHUNKS = 16;
 __global__ __launch_bounds__(LOSS_NT) void k_loss(const float* out, long long sOut, int ldo, const float* Y, int B,
                                                   int dout, const float* ymu, const float* ysd, bf16* dY,
-                                                  long long sdY, int Mp, float* loss) {
+                                                  long long sdY, int Mp, float* part) {
   __shared__ float sh[LOSS_NT];
-  const int mem = blockIdx.x;
+  const int chunk = blockIdx.x, mem = blockIdx.y;
   const float inv = 1.0f / (float)(B * dout);
+  const int rows = Mp / LOSS_CHUNKS, e0 = chunk * rows * ldo, e1 = e0 + rows * ldo;
   float acc = 0.0f;
-  for (long long e = threadIdx.x; e < (long long)Mp * ldo; e += LOSS_NT) {
-    const int m = (int)(e / ldo), n = (int)(e % ldo);
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += LOSS_NT) {
+    const int m = e / ldo, n = e - m * ldo;
     float gr = 0.0f;
     if (m < B && n < dout) {
       const float yn = (Y[(long long)m * dout + n] - ymu[n]) / ysd[n];
@@ -224,28 +235,55 @@ __global__ __launch_bounds__(LOSS_NT) void k_loss(const float* out, long long sO
     if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[mem] = sh[0] * inv;
+  if (threadIdx.x == 0) part[mem * LOSS_CHUNKS + chunk] = sh[0];
 }
 
-// bias gradient: column sums of the BF16 output gradient.  A block takes 64 columns of one member
-// with COLSUM_RG row groups (group g sums rows g, g + COLSUM_RG, ...; a wave reads 64 consecutive
-// columns of a row); the group sums meet in LDS and are added in group order (deterministic).
+__global__ void k_loss_total(const float* part, int K, float inv, float* loss) {
+  const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+  if (mem >= K) return;
+  float t = 0.0f;
+  for (int c = 0; c < LOSS_CHUNKS; ++c) t += part[mem * LOSS_CHUNKS + c];
+  loss[mem] = t * inv;
+}
+
+// out[member][r][c] = the sum, over the S partial results in order, of part[s][member][r][c]
+// (R x C values per member): the second stage of the split reductions
+__global__ void k_sum_splits(const float* part, int S, int nmem, int R, int C, float* out, long long ldo,
+                             long long sOut) {
+  const long long per = (long long)R * C;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per * nmem) return;
+  const int mem = (int)(e / per);
+  const long long rc = e - mem * per;
+  const int r = (int)(rc / C), c = (int)(rc - (long long)r * C);
+  float t = 0.0f;
+  for (int s = 0; s < S; ++s) t += part[((long long)s * nmem + mem) * per + rc];
+  out[mem * sOut + (long long)r * ldo + c] = t;
+}
+
+// bias gradient: column sums of the BF16 output gradient.  Block (x, member, range) takes 64
+// columns of one member over rows [range Mp / S, (range + 1) Mp / S) with COLSUM_RG row groups
+// (group g sums every COLSUM_RG-th row; a wave reads 64 consecutive columns of a row); the group
+// sums meet in LDS and are added in group order, and the S range sums go to part[range][member][n]
+// for k_sum_splits (S = 1: straight to gb).  Deterministic.
 constexpr int COLSUM_RG = 16;
 __global__ __launch_bounds__(64 * COLSUM_RG) void k_colsum(const bf16* dZ, long long sdZ, int Mp, int ld,
-                                                           float* gb, long long sgb) {
-  __shared__ float part[COLSUM_RG][64];
-  const int mem = blockIdx.y;
+                                                           float* gb, long long sgb, int S, float* part) {
+  __shared__ float sum[COLSUM_RG][64];
+  const int mem = blockIdx.y, range = blockIdx.z;
   const int c = threadIdx.x % 64, grp = threadIdx.x / 64;
   const int n = blockIdx.x * 64 + c;
+  const int rows = Mp / S, m0 = range * rows;
   float s = 0.0f;
   if (n < ld)
-    for (int m = grp; m < Mp; m += COLSUM_RG) s += (float)dZ[mem * sdZ + (long long)m * ld + n];
-  part[grp][c] = s;
+    for (int m = m0 + grp; m < m0 + rows; m += COLSUM_RG) s += (float)dZ[mem * sdZ + (long long)m * ld + n];
+  sum[grp][c] = s;
   __syncthreads();
   if (grp == 0 && n < ld) {
     float t = 0.0f;
-    for (int g = 0; g < COLSUM_RG; ++g) t += part[g][c];
-    gb[mem * sgb + n] = t;
+    for (int g = 0; g < COLSUM_RG; ++g) t += sum[g][c];
+    if (S == 1) gb[mem * sgb + n] = t;
+    else part[((long long)range * gridDim.y + mem) * ld + n] = t;
   }
 }
 

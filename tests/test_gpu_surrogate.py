@@ -61,16 +61,18 @@ def test_forward_members_and_ensemble(env, B):
     assert np.abs(var.cpu().numpy() - v_ref).max() <= 3e-2 * v_ref.max() + 1e-4 * scale ** 2
 
 
-def test_train_step_gradients_loss_and_adam(env):
+@pytest.mark.parametrize("B", [200, 2048])
+def test_train_step_gradients_loss_and_adam(env, B):
+    # 2048 rows split the gradient reductions over the batch into 8 ranges (200 rows: one)
     torch, rsur = env
     kw = dict(din=153, width=256, depth=4, dout=6)
-    net, params = make(rsur, kw, 2, seed=5)
-    X, Y = regression_data(200, 153, 6, seed=3)
+    net, params = make(rsur, kw, 2, seed=5, max_batch=max(512, B))
+    X, Y = regression_data(B, 153, 6, seed=3)
     Y = Y * 2.0 + 1.0
     x_mu, x_sd, y_mu, y_sd = X.mean(0), X.std(0), Y.mean(0), Y.std(0)
     net.set_norm(x_mu, x_sd, y_mu, y_sd)
     Xd, Yd = dev(torch, X), dev(torch, Y)
-    loss = net.train_step(Xd.data_ptr(), Yd.data_ptr(), 200, 1e-3)
+    loss = net.train_step(Xd.data_ptr(), Yd.data_ptr(), B, 1e-3)
     Xn, Yn = (X - x_mu) / x_sd, (Y - y_mu) / y_sd
     for k in range(2):
         Yp, cache = S.forward(params[k], net.dims, Xn)
