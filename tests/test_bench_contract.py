@@ -50,6 +50,7 @@ def test_cpu_baseline_is_the_oracle_on_a_bounded_sample():
     cb, s = bench.oracle_sample(p, cells, np.eye(3)[None], 10, "one small cell", seconds=0.2)
     assert cb["kind"] == "oracle" and cb["unit"] == "atom-steps/s" and cb["value"] > 0
     assert cb["cores"] >= 1 and "200 atoms" in cb["sample"]
+    assert cb["single_core_value"] > 0 and cb["host_threads"] >= 1 and cb["cpu_model"]
     assert s.shape == (1, 6) and np.all(np.isfinite(s))
 
 
