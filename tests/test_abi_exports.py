@@ -56,3 +56,45 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu(lib):
     assert L.rcell_create(ctypes.byref(p), None, 0, None, ctypes.byref(out)) == rcell.ERR_ARG
     assert out.value is None
     assert b"ncells" in L.rcell_last_error(None)
+
+
+def test_create_rejects_bad_parameters_and_cells_on_the_host(lib):
+    # each rejection happens before any device call (no context is left behind, none is needed)
+    import numpy as np
+    from paper_1902_09171_amd import rcell
+    from synth import configs
+    L = rcell.load()
+    cell = configs.kg_cell([20] * 10, 7)
+    x = np.ascontiguousarray(cell["x"], np.float64)
+    H0 = np.ascontiguousarray(cell["H0"], np.float64)
+
+    def create(p, natoms=len(x), H=H0):
+        init = (rcell.CellInit * 1)()
+        init[0].natoms = natoms
+        init[0].nbonds = 0
+        init[0].H0 = H.ctypes.data
+        init[0].x = x.ctypes.data
+        out = ctypes.c_void_p()
+        code = L.rcell_create(ctypes.byref(rcell.params_struct(p)), init, 1, None, ctypes.byref(out))
+        assert out.value is None
+        return code, L.rcell_last_error(None).decode()
+
+    kg = configs.kg_params()
+    cases = [
+        (dict(kg, potential=7), rcell.ERR_ARG, "unknown potential"),
+        (dict(kg, precision=5), rcell.ERR_ARG, "unknown precision"),
+        (dict(kg, dt=0.0), rcell.ERR_ARG, "dt"),
+        (dict(kg, lj_sigma=0.0), rcell.ERR_ARG, "lj_sigma"),
+        (configs.cu_params(sc_n=40), rcell.ERR_ARG, "Sutton-Chen"),
+    ]
+    for p, code, words in cases:
+        got, msg = create(p)
+        assert got == code and words in msg, (p, got, msg)
+    got, msg = create(kg, natoms=0)
+    assert got == rcell.ERR_ARG and "cell 0" in msg
+    sheared = H0.copy()
+    sheared[1, 0] = 0.5                                  # below the diagonal: not upper triangular
+    got, msg = create(kg, H=np.ascontiguousarray(sheared))
+    assert got == rcell.ERR_ARG and "upper triangular" in msg
+    got, msg = create(dict(kg, skin=0.5 * H0[0, 0]))     # rc + skin beyond half the box width
+    assert got == rcell.ERR_BOX and "box too small" in msg
