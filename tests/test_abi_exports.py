@@ -98,3 +98,15 @@ def test_create_rejects_bad_parameters_and_cells_on_the_host(lib):
     assert got == rcell.ERR_ARG and "upper triangular" in msg
     got, msg = create(dict(kg, skin=0.5 * H0[0, 0]))     # rc + skin beyond half the box width
     assert got == rcell.ERR_BOX and "box too small" in msg
+
+
+def test_surrogate_create_rejects_bad_shapes_on_the_host(lib):
+    from paper_1902_09171_amd import rcell
+    L = rcell.load()
+    L.rsur_last_error.restype = ctypes.c_char_p
+    for din, width, depth, dout, K, B in ((0, 256, 4, 6, 5, 256), (153, 256, 4, 0, 5, 256), (153, 0, 4, 6, 5, 256),
+                                          (153, 256, -1, 6, 5, 256), (153, 256, 4, 6, 0, 256), (153, 256, 4, 6, 5, 0)):
+        out = ctypes.c_void_p()
+        code = L.rsur_create(din, width, depth, dout, K, B, None, ctypes.byref(out))
+        assert code == rcell.ERR_ARG and out.value is None, (din, width, depth, dout, K, B)
+        assert b"din, dout, ensemble" in L.rsur_last_error(None)
