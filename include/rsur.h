@@ -27,7 +27,10 @@ extern "C" {
 typedef struct rsur_ctx rsur_ctx;
 
 /* Allocate a K-member ensemble for batches of up to max_batch rows on the current device.
- * Parameters start at zero: load them with rsur_set_params.  Normalisation starts as identity. */
+ * Parameters start at zero: load them with rsur_set_params.  Normalisation starts as identity.
+ * All device memory is allocated here (parameters, Adam moments, activations for max_batch rows,
+ * and the partial sums of the training step's split reductions: 8 x K x the largest layer's
+ * weights, in FP32); the forward and training calls allocate nothing. */
 int rsur_create(int32_t din, int32_t width, int32_t depth, int32_t dout, int32_t ensemble,
                 int32_t max_batch, void* hip_stream, rsur_ctx** out);
 int rsur_destroy(rsur_ctx* ctx);
@@ -58,7 +61,9 @@ int rsur_forward_members(rsur_ctx* ctx, const void* X_dev, int32_t B, void* out_
 
 /* One Adam step of every member on the same minibatch (raw X_dev B x din, raw Y_dev B x dout,
  * FP32), learning rate lr.  loss: host array of K floats receiving each member's MSE on the
- * normalised outputs before the step (synchronises), or NULL (enqueue only). */
+ * normalised outputs before the step (synchronises), or NULL (enqueue only).  The reductions over
+ * the minibatch (weight and bias gradients, loss) are split over blocks for large B and their
+ * partial sums added in a fixed order, so a step is reproducible bit for bit. */
 int rsur_train_step(rsur_ctx* ctx, const void* X_dev, const void* Y_dev, int32_t B, float lr, float* loss);
 
 #ifdef __cplusplus
