@@ -23,16 +23,20 @@ def _pairset(ij, d):
     return sorted((int(a), int(b), *np.round(v, 9)) for (a, b), v in zip(ij, d))
 
 
-@pytest.mark.parametrize("box", ["cubic", "skewed", "tiny"])
+@pytest.mark.parametrize("box", ["cubic", "skewed", "skewed_bins", "tiny"])
 def test_pair_set_matches_brute_force(box):
     rng = np.random.default_rng(1)
     if box == "cubic":
         H = np.eye(3) * 6.0
     elif box == "skewed":
         H = np.array([[6.0, 2.5, -1.7], [0.0, 5.5, 2.2], [0.0, 0.0, 6.3]])
+    elif box == "skewed_bins":
+        # wide enough for the cell list; the tilt makes the perpendicular width along x (6.57) a
+        # whole bin narrower than the edge (8): 3 bins of >= rc, where the edge would allow 4
+        H = np.array([[8.0, 3.6, -2.5], [0.0, 7.5, 3.2], [0.0, 0.0, 8.0]])
     else:   # rc larger than half the box: several images of the same pair, self images
         H = np.array([[2.0, 0.6, 0.3], [0.0, 2.2, -0.5], [0.0, 0.0, 1.9]])
-    n = 60 if box != "tiny" else 5
+    n = {"tiny": 5, "skewed_bins": 300}.get(box, 60)
     x = rng.uniform(0, 1, (n, 3)) @ H.T
     rc = 1.9
     ij, d = core.pairs(H, x, rc)

@@ -1,6 +1,7 @@
 """Plants plausible mistakes in a copy of the oracle (on the CPU) and checks that its pins catch
 each one: a pinned oracle must fail when a term is dropped, a sign flipped, an index or an
-operand order changed.  Each mutant is compiled to a temporary library and the relevant pin
+operand order changed.  Each mutant of the C oracle is compiled to a temporary library, each
+mutant of the numpy surrogate oracle is loaded in place of oracle.surrogate, and the relevant pin
 file is run against it in a subprocess."""
 import os
 import subprocess
@@ -32,7 +33,50 @@ MUTANTS = [
     ("full kick instead of half kick", "double h = p->dt / (2.0 * p->mass * p->mvv2e);",
      "double h = p->dt / (p->mass * p->mvv2e);", "dynamics"),
     ("Philox Weyl constant", "k0 += 0x9E3779B9u;", "k0 += 0x9E3779B7u;", "philox"),
+    # the cell-list branch of the pair search: bins narrower than the cutoff in a skewed box, and a
+    # stencil that misses the neighbouring bin below
+    ("bin count from the box edge instead of the perpendicular width",
+     "for (int k = 0; k < 3; ++k) nb[k] = (int)floor(w[k] / rc);",
+     "for (int k = 0; k < 3; ++k) nb[k] = (int)floor(H[4 * k] / rc);", "forces"),
+    ("stencil skips the lower z bin", "for (int o2 = -1; o2 <= 1; ++o2) {", "for (int o2 = 0; o2 <= 1; ++o2) {",
+     "forces"),
 ]
+
+SUR_SRC = os.path.join(ROOT, "oracle", "surrogate.py")
+SUR_MUTANTS = [
+    ("ensemble variance scaled by y_sd instead of y_sd^2",
+     "    outs = np.stack([forward(p, dims, Xn)[0] * y_sd + y_mu for p in params])\n"
+     "    return outs.mean(0), outs.var(0)",
+     "    outs = np.stack([forward(p, dims, Xn)[0] for p in params])\n"
+     "    return outs.mean(0) * y_sd + y_mu, outs.var(0) * y_sd"),
+    ("ensemble variance with K - 1 in the denominator", "return outs.mean(0), outs.var(0)",
+     "return outs.mean(0), outs.var(0, ddof=1)"),
+    ("input normalisation multiplies by the spread", "return (X - mu) / sd", "return (X - mu) * sd"),
+    ("SiLU derivative drops a factor", "return s * (1.0 + z * (1.0 - s))", "return s * (1.0 + z * s)"),
+    ("weight gradient of the wrong layer input", "gW[l] = acts[l].T @ dz", "gW[l] = acts[l + 1].T @ dz"),
+    ("Adam without bias correction", "mh = m / (1 - b1 ** t)", "mh = m"),
+]
+
+# loads the mutated file as oracle.surrogate, then runs the surrogate pins
+_SUR_BOOT = (
+    "import importlib.util, sys; import oracle; "
+    "spec = importlib.util.spec_from_file_location('oracle.surrogate', sys.argv[1]); "
+    "m = importlib.util.module_from_spec(spec); sys.modules['oracle.surrogate'] = m; "
+    "spec.loader.exec_module(m); oracle.surrogate = m; import pytest; "
+    "sys.exit(pytest.main(['-x', '-q', '-p', 'no:cacheprovider', sys.argv[2]]))")
+
+
+def _run_sur_mutant(m, tmp):
+    name, old, new = m
+    src = open(SUR_SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not unique or missing: {name}"
+    path = os.path.join(tmp, f"sur_{abs(hash(name))}.py")
+    with open(path, "w") as fh:
+        fh.write(src.replace(old, new))
+    r = subprocess.run([sys.executable, "-c", _SUR_BOOT, path,
+                        os.path.join(ROOT, "tests", "test_oracle_surrogate.py")],
+                       cwd=ROOT, capture_output=True, text=True, timeout=600)
+    return name, r.returncode
 
 
 def _run_mutant(m, tmp):
@@ -58,6 +102,17 @@ def _run_mutant(m, tmp):
 
 CONTROLS = [("unmutated copy", "int orc_threads(int32_t n) {", "int orc_threads(int32_t n) {", t)
             for t in ("forces", "coupling", "dynamics", "philox")]
+
+
+def test_surrogate_pins_catch_planted_mistakes():
+    with tempfile.TemporaryDirectory() as tmp:
+        with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+            results = list(ex.map(lambda m: _run_sur_mutant(m, tmp), SUR_MUTANTS + [("unmutated copy", "import numpy as np",
+                                                                                      "import numpy as np")]))
+    control = results[-1]
+    assert control[1] == 0, f"the harness fails on the unmutated surrogate oracle: {control}"
+    survivors = [name for name, rc in results[:-1] if rc == 0]
+    assert not survivors, f"mutants not caught by the pins: {survivors}"
 
 
 def test_pins_catch_planted_mistakes():

@@ -1,6 +1,7 @@
 """Pins for the FP64 surrogate oracle: central finite differences of the loss (backward pass),
 the least-squares closed form (a network without hidden layers trained with Adam converges to
-numpy.linalg.lstsq), Adam's first-step closed form, and the SiLU derivative."""
+numpy.linalg.lstsq), Adam's first-step closed form, the SiLU derivative, and the ensemble's
+de-normalised mean and (population) variance worked out by hand for three linear members."""
 import numpy as np
 import pytest
 
@@ -69,3 +70,23 @@ def test_ensemble_statistics():
     assert np.allclose(mu, outs.mean(0)) and np.allclose(var, outs.var(0))
     same_mu, same_var = S.ensemble_predict([params[0]] * 3, dims, X, 0.0, 1.0, 0.0, 1.0)
     assert np.allclose(same_var, 0.0)
+
+
+def test_ensemble_denormalisation_closed_form():
+    """Three members without hidden layers (y_n = x_n W + b), worked by hand.  The raw input
+    (3, -1) with x_mu = (1, 1), x_sd = (2, 4) normalises to (1, -0.5); the members then give
+    normalised outputs (1, -0.5), (2, 0) and (3, 0.5): per component mean (2, 0) and population
+    variance (2/3, 1/6).  De-normalising with y_mu = (10, -5), y_sd = (2, 3) shifts the mean to
+    (10 + 2 * 2, -5 + 3 * 0) = (14, -5) and scales the variance by y_sd^2 to (8/3, 3/2)."""
+    dims = S.layer_dims(2, 0, 0, 2)
+    members = [
+        (np.array([[1.0, 0.0], [0.0, 1.0]]), np.array([0.0, 0.0])),
+        (np.array([[2.0, 0.0], [0.0, 2.0]]), np.array([0.0, 1.0])),
+        (np.array([[3.0, 0.0], [0.0, 0.0]]), np.array([0.0, 0.5])),
+    ]
+    params = [S.flatten([W], [b]) for W, b in members]
+    X = np.array([[3.0, -1.0]])
+    mu, var = S.ensemble_predict(params, dims, X, np.array([1.0, 1.0]), np.array([2.0, 4.0]),
+                                 np.array([10.0, -5.0]), np.array([2.0, 3.0]))
+    assert np.allclose(mu, [[14.0, -5.0]], rtol=0, atol=1e-12)
+    assert np.allclose(var, [[8.0 / 3.0, 1.5]], rtol=0, atol=1e-12)
