@@ -2,7 +2,7 @@
 
 Workloads (``--workload``; every run prints one JSON line):
 
-  cu_element  (default) one hex8 element of copper: 8 FCC r-cells x 4000 atoms, Sutton-Chen EAM,
+  cu_element  one hex8 element of copper: 8 FCC r-cells x 4000 atoms, Sutton-Chen EAM,
               300 K Langevin, dt = 1 fs, mixed precision.  A step is one finite-element load step:
               the device-resident F of every cell is QR-decomposed and the boxes remapped, 100 MD
               steps run (neighbour builds, two-pass EAM forces fused with the Langevin
@@ -18,7 +18,7 @@ Workloads (``--workload``; every run prints one JSON line):
               batch followed by the stress read.
   kg_glassy   100 glassy Kremer-Grest cells of 100 x 100 beads (10^6 beads, the size of the paper's
               production run) with the LJ attraction to 2.5 sigma at T = 0.1.
-  fe_bar      the explicit hex8 bar (8 x 2 x 2 elements, 2 x 2 x 2 Gauss points = 256 r-cells of
+  fe_bar      (default) the explicit hex8 bar (8 x 2 x 2 elements, 2 x 2 x 2 Gauss points = 256 r-cells of
               400 x 100 beads, ~10.2 M beads) under uniaxial tension; a step is one FE load step
               (host FE update, F to the cells, 500 MD steps, stress back).
   fe_tet      the paper's polymer specimen (Sec. 3.2): a cube of 100 C3D4 tetrahedra with one
@@ -56,12 +56,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP32 = 157.3e12          # MI355X FP32 vector, FLOP/s (published)
 PEAK_HBM = 8.0e12             # MI355X HBM3E, bytes/s (published)
 PEAK_BF16 = 2.5e15            # MI355X dense BF16 matrix, FLOP/s (published)
-# Sutton-Chen: algorithmic FLOPs per unique pair inside the cutoff (FMA = 2, other ops 1): force
-# pass (separation 3, r^2 5, 1/r 2, a/r 1, t^6 3, t^9 2, pair scalar 7, forces on both atoms 12,
-# virial 15, pair energy 3) and density pass (separation 3, r^2 5, 1/r 2, a/r 1, t^6 3, shift 1,
-# both densities 2)
-FLOP_FORCE_PER_PAIR = 53
-FLOP_DENSITY_PER_PAIR = 17
+# Sutton-Chen: algorithmic FLOPs per unique pair inside the cutoff of an MD step that does not
+# report the energy (FMA = 2, every other arithmetic op 1), for a half-list evaluation from Cartesian
+# coordinates.  Force pass: separation d = x_j - x_i 3, r^2 5, 1/r 1, powers r^-2, r^-3, r^-6 3,
+# pair scalar g/r = -r^-2 r^-6 (eps n a^9 r^-3 + F'_i + F'_j) 5, t = (g/r) d 3, f_i += t and
+# f_j -= t 6, virial W += t (x) d 12: 38.  Density pass: separation 3, r^2 5, 1/r 1, r^-3 2,
+# r^-6 1, (a/r)^m 1, shift 1, both densities 2: 16.
+FLOP_FORCE_PER_PAIR = 38
+FLOP_DENSITY_PER_PAIR = 16
 PAIRS_PER_ATOM = 67           # unique neighbours within 1.95 a in FCC copper
 # Kremer-Grest: the least HBM traffic an MD step needs per bead: x and v in FP64, read and
 # written (96 B), plus the two chain partners as 32-bit indices (8 B)
@@ -70,7 +72,7 @@ BYTES_PER_BEAD_STEP = 104
 ORACLE_SECONDS = 10.0     # CPU time the oracle baseline runs for (bounded sample of the workload)
 DEFAULTS = {"cu_element": (50, 3), "cu_batched": (10, 2), "kg_single": (1000, 100), "kg_batched": (10, 1),
             "kg_glassy": (10, 1),
-            "fe_bar": (4, 1), "fe_tet": (4, 1), "fe_scaling": (3, 1), "glassy_rates": (4000, 100),
+            "fe_bar": (10, 2), "fe_tet": (4, 1), "fe_scaling": (3, 1), "glassy_rates": (4000, 100),
             "surrogate": (200, 20)}
 
 
@@ -112,7 +114,7 @@ def oracle_sample(params, cells, F, nsteps, label, seconds=None):
     over every step.  Returns (cpu_baseline dict, oracle stress after nsteps)."""
     from oracle import core
     seconds = ORACLE_SECONDS if seconds is None else seconds
-    threads = core.threads(min(len(cells), os.cpu_count() or 1))
+    threads = core.threads(min(len(cells), host_threads()))
     ob = core.OracleBatch(params, cells)
     ob.set_deformation(F)
     ob.get_stress()
@@ -141,7 +143,19 @@ def oracle_sample(params, cells, F, nsteps, label, seconds=None):
     return dict(value=value, unit="atom-steps/s", cores=threads, kind="oracle",
                 sample=f"{len(cells)} cells, {natoms} atoms, {total} MD steps in {dt:.1f} s ({label}; "
                        f"stress compared with the GPU after the first {nsteps})",
-                single_core_value=single, host_threads=os.cpu_count(), cpu_model=cpu_model()), s_ora
+                single_core_value=single, host_threads=host_threads(), cpu_model=cpu_model()), s_ora
+
+
+def host_threads():
+    """Hardware threads this process may use: the CPU affinity mask, capped by OMP_NUM_THREADS."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
 
 
 def cpu_model():
@@ -249,10 +263,10 @@ def bench_cu_element(args, torch, rcell, configs, ncells=8):
                    "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
                    "lanes_per_atom": lanes}, roofline)
     if not args.no_cpu_baseline:
-        sub = list(range(8))
+        sub = list(range(min(ncells, max(8, host_threads()))))
         cells8, F8 = [cfg["cells"][c] for c in sub], cfg["F_path"][0][sub]
         cb, s_ora = oracle_sample(cfg["params"], cells8, F8, args.cpu_sample_steps,
-                                  "first load step of the first 8 cells")
+                                  f"first load step of the first {len(sub)} cells")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cells8, F8,
                                                            args.cpu_sample_steps, s_ora, lanes)
@@ -405,8 +419,9 @@ def bench_kg_batched(args, torch, rcell, configs, glassy=False):
                    "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_STEP,
                    "lanes_per_atom": lanes, "rebuilds": g.rebuilds()}, roofline)
     if not args.no_cpu_baseline:
-        sub = list(range(16))
-        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F[sub], 20, "the first 16 cells of the batch")
+        sub = list(range(min(ncells, max(16, host_threads()))))
+        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F[sub], 20,
+                                  f"the first {len(sub)} cells of the batch")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F[sub], 20,
                                                            s_ora, lanes)
@@ -553,9 +568,10 @@ def bench_fe(args, torch, rcell, configs, name):
                    "lanes_per_atom": lanes, "rebuilds": md.g.rebuilds()}, roofline,
                   extra={"fe_wall_s_per_load_step": elapsed / args.steps})
     if not args.no_cpu_baseline:
-        sub = list(range(4))
+        sub = list(range(min(len(cells), host_threads())))
         F = np.stack([np.eye(3)] * len(sub))
-        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F, 20, "4 of the r-cells, from rest")
+        cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F, 20,
+                                  f"{len(sub)} of the r-cells (one per host thread), from rest")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F, 20,
                                                            s_ora, lanes)
@@ -646,7 +662,7 @@ WORKLOADS = {"cu_element": bench_cu_element, "cu_batched": bench_cu_batched, "kg
 def main():
     global ORACLE_SECONDS
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="cu_element", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fe_bar", choices=sorted(WORKLOADS))
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
