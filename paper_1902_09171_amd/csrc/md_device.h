@@ -64,7 +64,7 @@ struct CellDev {
   int rebuild, pending, status, pad;
   double Hb[6];                   // H at the last neighbour build, upper triangle (0 1 2 4 5 8)
   float hs2;                      // squared displacement that still keeps the list complete
-  int pad2;
+  float dmax2;                    // largest squared displacement since the last build, as last reduced
   // molecular statics (FIRE): time step, mixing parameter, the velocity update of this iteration
   // (v = fa v + fb f, or zero when frozen), iterations since the power last turned negative,
   // converged flag and iterations used
@@ -119,6 +119,10 @@ struct MDArgs {
   int ntiles, ncells;
   int* abin; int* bcount; int* bstart; int* bnum; int* bfill; int* binned; int* sort_tmp;
   long long bins_total;
+  // work list of the rebuild phases (k_rebuild_work): the cells flagged for a rebuild in cell
+  // order, and the exclusive prefix sums of their tiles and of their 64-bin chunks (ncell + 1
+  // entries each); work_count[0..2] = cells, tiles, chunks
+  int *work_cells, *work_tstart, *work_kstart, *work_count;
   // integrator constants (computed once on the host, documented expressions)
   double dt, h, drag, c24, mmv, half_skin2, rcs2;
   double fire_ftol2;               // statics: converged when max_i |f_i|^2 <= fire_ftol2
@@ -194,6 +198,17 @@ struct Mixed {
     d[2] = (float)(g.h[5] * c);
   }
   __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) { sep(sj, si, geo(C), d); }
+  // the same separation, also kept in FP64 before the rounding: the pair virial is accumulated
+  // from it in FP64, so neither the rounding of d nor FP32 sums enter the stress
+  __device__ static void sep2(const S& sj, const S& si, const Geo& g, R d[3], double dd[3]) {
+    const double a = (double)(int)((unsigned)sj.x - (unsigned)si.x);
+    const double b = (double)(int)((unsigned)sj.y - (unsigned)si.y);
+    const double c = (double)(int)((unsigned)sj.z - (unsigned)si.z);
+    dd[0] = fma(g.h[0], a, fma(g.h[1], b, g.h[2] * c));
+    dd[1] = fma(g.h[3], b, g.h[4] * c);
+    dd[2] = g.h[5] * c;
+    d[0] = (float)dd[0]; d[1] = (float)dd[1]; d[2] = (float)dd[2];
+  }
   // single hardware instructions (about 1 ulp): ample for FP32 pair forces
   __device__ static R rsq(R x) { return __builtin_amdgcn_rsqf(x); }
   __device__ static R rcp(R x) { return __builtin_amdgcn_rcpf(x); }
@@ -238,6 +253,10 @@ struct FP64 {
     d[2] = g.h[5] * c;
   }
   __device__ static void sep(const S& sj, const S& si, const CellDev& C, R d[3]) { sep(sj, si, geo(C), d); }
+  __device__ static void sep2(const S& sj, const S& si, const Geo& g, R d[3], double dd[3]) {
+    sep(sj, si, g, d);
+    dd[0] = d[0]; dd[1] = d[1]; dd[2] = d[2];
+  }
   __device__ static R rsq(R x) { return 1.0 / sqrt(x); }
   __device__ static R rcp(R x) { return 1.0 / x; }
 };
@@ -549,6 +568,14 @@ __device__ __forceinline__ void part_values(const MDArgs& a, int mode, const dou
   for (int q = 0; q < 6; ++q) V[q] = mode == MODE_STATIC ? K[q] : W[q] - kin * K[q];
 }
 
+// Twice the pair virial of one listed pair, g d (x) d / r with gr = g / r, accumulated in FP64 from
+// the FP64 separation (halved once after the loop, exact in binary).
+__device__ __forceinline__ void add_virial(double w[6], double gr, const double dd[3]) {
+  const double t0 = gr * dd[0], t1 = gr * dd[1], t2 = gr * dd[2];
+  w[0] = fma(t0, dd[0], w[0]); w[1] = fma(t1, dd[1], w[1]); w[2] = fma(t2, dd[2], w[2]);
+  w[3] = fma(t0, dd[1], w[3]); w[4] = fma(t0, dd[2], w[4]); w[5] = fma(t1, dd[2], w[5]);
+}
+
 // ------------------------------------------------------------------ force kernels
 // List entries of one trip: UNR consecutive entries of one list block, as 32-bit words loaded with
 // one vector load (the trip's first entry is a multiple of UNR, so they are aligned).
@@ -618,7 +645,8 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   const bool skip = (mode == MODE_PRIME && !C.pending) || (mode == MODE_STATIC && C.fdone);
   const bool active = slot < t.count && !skip;
   const long long i = (long long)t.begin + slot;
-  R f[3] = {0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
+  R f[3] = {0, 0, 0}, pe = 0;
+  double w[6] = {0, 0, 0, 0, 0, 0};
   int status = 0;
   if (active) {
     const typename P::S si = P::load(a.s_cur, i);
@@ -635,7 +663,8 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
           R d[3];
-          P::sep(sj[u], si, g, d);
+          double dd[3];
+          P::sep2(sj[u], si, g, d, dd);
           const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
           const bool in = ok[u] && r2 < rc2;
           const R r2i = P::rcp(r2);
@@ -643,9 +672,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
           const R s6 = s2 * s2 * s2;
           const R gr = in ? -e24 * (s6 * ((R)2 * s6 - (R)1)) * r2i : (R)0;   // (dU/dr) / r
           f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-          // twice the pair virial; halved once after the loop (exact)
-          w[0] += gr * d[0] * d[0]; w[1] += gr * d[1] * d[1]; w[2] += gr * d[2] * d[2];
-          w[3] += gr * d[0] * d[1]; w[4] += gr * d[0] * d[2]; w[5] += gr * d[1] * d[2];
+          add_virial(w, (double)gr, dd);
           if constexpr (decltype(with_pe)::value) pe += in ? (R)0.5 * (e4 * s6 * (s6 - (R)1) - sh) : (R)0;
         }
       }
@@ -660,21 +687,21 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
       for (int q = 0; q < 4; ++q) {
         if (bp[q] < 0) continue;
         R d[3];
-        P::sep(P::load_rel(sc, bp[q]), si, g, d);
+        double dd[3];
+        P::sep2(P::load_rel(sc, bp[q]), si, g, d, dd);
         const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         const R tt = r2 / R02;
         if (!(tt < (R)1)) { status = ST_BOND; continue; }
         const R gr = K / ((R)1 - tt);
         f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-        w[0] += gr * d[0] * d[0]; w[1] += gr * d[1] * d[1]; w[2] += gr * d[2] * d[2];
-        w[3] += gr * d[0] * d[1]; w[4] += gr * d[0] * d[2]; w[5] += gr * d[1] * d[2];
+        add_virial(w, (double)gr, dd);
         pe += (R)(-0.25 * a.fene_K * a.fene_R02) * (R)log((double)((R)1 - tt));
       }
     }
   }
   double W[6], K[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 6; ++q) W[q] = 0.5 * (double)lane_sum<TPA>(w[q]);
+  for (int q = 0; q < 6; ++q) W[q] = 0.5 * lane_sum<TPA>(w[q]);
   double PE = (double)lane_sum<TPA>(pe);
   const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
   long long xi[3] = {0, 0, 0};
@@ -772,7 +799,8 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   const int slot = threadIdx.x / TPA, lane = threadIdx.x % TPA;
   const bool active = slot < t.count && !(mode == MODE_PRIME && !C.pending) && !(mode == MODE_STATIC && C.fdone);
   const long long i = (long long)t.begin + slot;
-  R f[3] = {0, 0, 0}, w[6] = {0, 0, 0, 0, 0, 0}, pe = 0;
+  R f[3] = {0, 0, 0}, pe = 0;
+  double w[6] = {0, 0, 0, 0, 0, 0};
   R fpi = 0;
   if (active) {
     const typename P::S si = P::load(a.s_cur, i);
@@ -793,7 +821,8 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
           R d[3];
-          P::sep(sj[u], si, g, d);
+          double dd[3];
+          P::sep2(sj[u], si, g, d, dd);
           const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
           const bool in = ok[u] && r2 < rc2;
           const R ri = P::rsq(r2);
@@ -809,9 +838,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
           }
           const R gr = in ? g0 : (R)0;
           f[0] += gr * d[0]; f[1] += gr * d[1]; f[2] += gr * d[2];
-          // twice the pair virial; halved once after the loop (exact)
-          w[0] += gr * d[0] * d[0]; w[1] += gr * d[1] * d[1]; w[2] += gr * d[2] * d[2];
-          w[3] += gr * d[0] * d[1]; w[4] += gr * d[0] * d[2]; w[5] += gr * d[1] * d[2];
+          add_virial(w, (double)gr, dd);
           if constexpr (decltype(with_pe)::value) {
             if constexpr (SN == 9 && SM == 6) pe += in ? eh9 * tn - eh * phic : (R)0;
             else pe += in ? eh * (tn - phic) : (R)0;
@@ -824,7 +851,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_eam(MDArgs a, int mode) {
   }
   double W[6], K[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int q = 0; q < 6; ++q) W[q] = 0.5 * (double)lane_sum<TPA>(w[q]);
+  for (int q = 0; q < 6; ++q) W[q] = 0.5 * lane_sum<TPA>(w[q]);
   double PE = (double)lane_sum<TPA>(pe);
   const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
   long long xi[3] = {0, 0, 0};
@@ -1031,6 +1058,7 @@ __device__ __forceinline__ void reduce_cell(const MDArgs& a, int cell, int mode,
   if (st != 0 && cstatus == 0) C.status = st;
   if (mode == RED_MOVE) {                // statics: positions moved; rebuild when they left the skin
     C.rebuild = md > chs2;
+    C.dmax2 = md;
     return;
   }
   if (mode == RED_STATIC) {              // statics: one FIRE decision per cell (same order as the oracle)
@@ -1054,6 +1082,7 @@ __device__ __forceinline__ void reduce_cell(const MDArgs& a, int cell, int mode,
   if (crebuild) C.nrebuild = cnreb + 1;
   if (mode == RED_START) {
     C.rebuild = md > chs2;
+    C.dmax2 = md;
     C.xi_mean[0] = (double)x0 / (double)cn;
     C.xi_mean[1] = (double)x1 / (double)cn;
     C.xi_mean[2] = (double)x2 / (double)cn;
@@ -1076,6 +1105,7 @@ __device__ __forceinline__ void reduce_cell(const MDArgs& a, int cell, int mode,
   C.step = cstep + 1;
   if (mode == RED_STEP) {
     C.rebuild = md > chs2;
+    C.dmax2 = md;
     C.xi_mean[0] = (double)x0 / (double)cn;
     C.xi_mean[1] = (double)x1 / (double)cn;
     C.xi_mean[2] = (double)x2 / (double)cn;
@@ -1122,18 +1152,70 @@ __device__ __forceinline__ void bin_atom(const MDArgs& a, const CellDev& C, long
   atomicAdd(&a.bcount[C.bin_off + bin], 1);
 }
 
+// Tile phases of a rebuild walk the work list: WORK_WAVES tiles per block, one wave per tile,
+// block-strided over the tiles of the rebuilding cells, so a step in which few cells rebuild
+// launches a small grid instead of one block per tile of the batch.
+constexpr int WORK_WAVES = 4;
+// the k with start[k] <= w < start[k + 1] in a strictly increasing prefix array of n + 1 entries
+__device__ __forceinline__ int work_find(const int* start, int n, int w) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+// batch tile index of the w-th tile of the rebuild work list
+__device__ __forceinline__ int work_tile(const MDArgs& a, int w) {
+  const int k = work_find(a.work_tstart, a.work_count[0], w);
+  return a.cells[a.work_cells[k]].tile_off + (w - a.work_tstart[k]);
+}
+template <class Fn>
+__device__ __forceinline__ void for_work_tiles(const MDArgs& a, Fn&& fn) {
+  const int nt = a.work_count[1];
+  const int lane = threadIdx.x & 63;
+  for (int k = blockIdx.x * WORK_WAVES + (threadIdx.x >> 6); k < nt; k += gridDim.x * WORK_WAVES) {
+    const Tile t = a.tiles[work_tile(a, k)];
+    if (lane < t.count) fn(t, (long long)t.begin + lane);
+  }
+}
+
 template <class P>
-__global__ __launch_bounds__(TILE) void k_bin(MDArgs a) {
-  const int tb = block_tile(a.ntiles, blockIdx.x);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
-  const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  bin_atom<P>(a, C, (long long)t.begin + threadIdx.x);
+__global__ __launch_bounds__(TILE * WORK_WAVES) void k_bin(MDArgs a) {
+  for_work_tiles(a, [&](const Tile& t, long long i) { bin_atom<P>(a, a.cells[t.cell], i); });
 }
 
 constexpr int SCAN_NT = 1024;
-// exclusive scan of one cell's histogram by a block of SCAN_NT threads (sh: SCAN_NT ints of LDS)
+// Exclusive scan of one value per thread over a block of SCAN_NT threads: an inclusive scan inside
+// each wave by shuffles, the 16 wave totals scanned by the first wave through LDS (wsum: 16 ints),
+// two barriers.  Returns the exclusive prefix; *total receives the block's sum.
+__device__ __forceinline__ int block_exscan(int v, int* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  if (wv == 0) {
+    int w = lane < SCAN_NT / 64 ? wsum[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < SCAN_NT / 64; o <<= 1) {
+      const int y = __shfl_up(w, o);
+      if (lane >= o) w += y;
+    }
+    if (lane < SCAN_NT / 64) wsum[lane] = w;
+  }
+  __syncthreads();
+  const int before = wv > 0 ? wsum[wv - 1] : 0;
+  *total = wsum[SCAN_NT / 64 - 1];
+  __syncthreads();                 // wsum is reused by the next call
+  return before + inc - v;
+}
+
+// exclusive scan of one cell's histogram by a block of SCAN_NT threads (sh: at least 16 ints of LDS)
 __device__ __forceinline__ void scan_cell(const MDArgs& a, CellDev& C, int* sh) {
   const int nbins = C.nb[0] * C.nb[1] * C.nb[2];
   const int t = threadIdx.x;
@@ -1141,35 +1223,64 @@ __device__ __forceinline__ void scan_cell(const MDArgs& a, CellDev& C, int* sh) 
     const int up[6] = {0, 1, 2, 4, 5, 8};
     for (int q = 0; q < 6; ++q) C.Hb[q] = C.H[up[q]];
     C.hs2 = (float)a.half_skin2;
+    C.dmax2 = 0.f;
   }
   int carry = 0;
   for (int base = 0; base < nbins; base += SCAN_NT) {   // coalesced chunks of SCAN_NT bins
     const int b = base + t;
     const int c = b < nbins ? a.bcount[C.bin_off + b] : 0;
-    sh[t] = c;
-    __syncthreads();
-    for (int o = 1; o < SCAN_NT; o <<= 1) {            // Hillis-Steele inclusive scan
-      const int v = t >= o ? sh[t - o] : 0;
-      __syncthreads();
-      sh[t] += v;
-      __syncthreads();
-    }
+    int tot;
+    const int ex = block_exscan(c, sh, &tot);
     if (b < nbins) {
-      a.bstart[C.bin_off + b] = carry + sh[t] - c;
+      a.bstart[C.bin_off + b] = carry + ex;
       a.bnum[C.bin_off + b] = c;
       a.bfill[C.bin_off + b] = 0;
       a.bcount[C.bin_off + b] = 0;                        // ready for the next build
     }
-    carry += sh[SCAN_NT - 1];
-    __syncthreads();
+    carry += tot;
   }
+  __syncthreads();                 // the starts are read by other threads of a fused caller
 }
 
+// one block per rebuilding cell, block-strided over the work list
 __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
-  __shared__ int sh[SCAN_NT];
-  CellDev& C = a.cells[blockIdx.x];
-  if (!C.rebuild) return;
-  scan_cell(a, C, sh);
+  __shared__ int sh[SCAN_NT / 64];
+  for (int k = blockIdx.x; k < a.work_count[0]; k += gridDim.x) scan_cell(a, a.cells[a.work_cells[k]], sh);
+}
+
+// The work list of a rebuild: the cells flagged for one, in cell order, with the prefix sums of
+// their tiles and of their 64-bin chunks (a cell's bins start at a multiple of 64, so a chunk
+// belongs to one cell).  One block of SCAN_NT threads: exclusive scans of the flags and counts.
+__global__ __launch_bounds__(SCAN_NT) void k_rebuild_work(MDArgs a) {
+  __shared__ int sh[SCAN_NT / 64];
+  int bc = 0, bt = 0, bk = 0;
+  for (int c0 = 0; c0 < a.ncells; c0 += SCAN_NT) {
+    const int c = c0 + threadIdx.x;
+    int fl = 0, nt = 0, nk = 0;
+    if (c < a.ncells) {
+      const CellDev& C = a.cells[c];
+      if (C.rebuild) {
+        fl = 1;
+        nt = C.ntile;
+        nk = (C.nb[0] * C.nb[1] * C.nb[2] + 63) / 64;
+      }
+    }
+    int tc, tt, tk;
+    const int ec = block_exscan(fl, sh, &tc);
+    const int et = block_exscan(nt, sh, &tt);
+    const int ek = block_exscan(nk, sh, &tk);
+    if (fl) {
+      a.work_cells[bc + ec] = c;
+      a.work_tstart[bc + ec] = bt + et;
+      a.work_kstart[bc + ec] = bk + ek;
+    }
+    bc += tc; bt += tt; bk += tk;
+  }
+  if (threadIdx.x == 0) {
+    a.work_tstart[bc] = bt;
+    a.work_kstart[bc] = bk;
+    a.work_count[0] = bc; a.work_count[1] = bt; a.work_count[2] = bk;
+  }
 }
 
 __device__ __forceinline__ void fill_atom(const MDArgs& a, const CellDev& C, long long i) {
@@ -1179,13 +1290,8 @@ __device__ __forceinline__ void fill_atom(const MDArgs& a, const CellDev& C, lon
   a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
 
-__global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
-  const int tb = block_tile(a.ntiles, blockIdx.x);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
-  const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  fill_atom(a, C, (long long)t.begin + threadIdx.x);
+__global__ __launch_bounds__(TILE * WORK_WAVES) void k_bin_fill(MDArgs a) {
+  for_work_tiles(a, [&](const Tile& t, long long i) { fill_atom(a, a.cells[t.cell], i); });
 }
 
 // one lane per bin slot of every cell (grid over the bin capacity), one wave per block.  Each bin
@@ -1197,16 +1303,14 @@ __global__ __launch_bounds__(TILE) void k_bin_fill(MDArgs a) {
 // scratch array.  Sorted keys are mapped back to current cell-local indices through pos_of.
 constexpr int SMALL_BIN = 24;
 constexpr int SORT_LDS_MAX = 16384;  // staged keys per wave at most (64 KB)
-__global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell, int cap) {
-  extern __shared__ int stage[];
-  const long long g = (long long)blockIdx.x * 64 + threadIdx.x;
+__device__ __forceinline__ void sort_chunk(const MDArgs& a, const int* bin_cell, int cap, long long g, int* stage) {
   int big = 0;                       // this lane's bin needs the wave
   int *p = nullptr, n = 0, off = 0;
-  if (g < a.bins_total) {
+  {
     const int c = bin_cell[g];
     const CellDev& C = a.cells[c];
     const int b = (int)(g - C.bin_off);
-    if (C.rebuild && b < C.nb[0] * C.nb[1] * C.nb[2]) {
+    if (b < C.nb[0] * C.nb[1] * C.nb[2]) {
       p = a.binned + C.off + a.bstart[g];
       n = a.bnum[g];
       off = C.off;
@@ -1266,6 +1370,17 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell, 
   for (int e = 0; e < n; ++e) p[e] = a.pos_of[off + p[e]];  // keys back to current indices
 }
 
+// one wave per 64-bin chunk of the rebuilding cells, block-strided over the work list
+__global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell, int cap) {
+  extern __shared__ int stage[];
+  for (int w = blockIdx.x; w < a.work_count[2]; w += gridDim.x) {
+    __syncthreads();                 // the previous chunk's keys have been read
+    const int k = work_find(a.work_kstart, a.work_count[0], w);
+    const long long chunk = a.cells[a.work_cells[k]].bin_off / 64 + (w - a.work_kstart[k]);
+    sort_chunk(a, bin_cell, cap, chunk * 64 + threadIdx.x, stage);
+  }
+}
+
 // Reorder the atoms of every rebuilding cell by (bin, original index): position q of the cell
 // receives the atom binned[q].  Phase 1 gathers positions, velocities, the fixed-point coordinates,
 // bin coordinates and original indices into the scratch rows and records pos_of; phase 2 copies
@@ -1298,13 +1413,8 @@ __device__ __forceinline__ void reorder_gather_atom(const MDArgs& a, const CellD
 }
 
 template <class P>
-__global__ __launch_bounds__(TILE) void k_reorder_gather(MDArgs a) {
-  const int tb = block_tile(a.ntiles, blockIdx.x);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
-  const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  reorder_gather_atom<P>(a, C, (long long)t.begin + threadIdx.x);
+__global__ __launch_bounds__(TILE * WORK_WAVES) void k_reorder_gather(MDArgs a) {
+  for_work_tiles(a, [&](const Tile& t, long long i) { reorder_gather_atom<P>(a, a.cells[t.cell], i); });
 }
 
 template <class P>
@@ -1328,13 +1438,8 @@ __device__ __forceinline__ void reorder_scatter_atom(const MDArgs& a, const Cell
 }
 
 template <class P>
-__global__ __launch_bounds__(TILE) void k_reorder_scatter(MDArgs a) {
-  const int tb = block_tile(a.ntiles, blockIdx.x);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
-  const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild || (int)threadIdx.x >= t.count) return;
-  reorder_scatter_atom<P>(a, C, (long long)t.begin + threadIdx.x);
+__global__ __launch_bounds__(TILE * WORK_WAVES) void k_reorder_scatter(MDArgs a) {
+  for_work_tiles(a, [&](const Tile& t, long long i) { reorder_scatter_atom<P>(a, a.cells[t.cell], i); });
 }
 
 // The six preparation phases of a rebuild (bin, scan, fill, sort, reorder gather and scatter) for
@@ -1420,15 +1525,9 @@ constexpr int LPA = 8;
 constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
 constexpr int MAX_RANGES = 18;   // 3 x 3 columns, each at most two ranges
 template <class P, class LT>
-__global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
-  constexpr int PER_TILE = TILE / BUILD_ATOMS;
-  __shared__ int2 rng[BUILD_ATOMS][MAX_RANGES];   // candidate ranges (first position, count) per atom
-  const int tb = block_tile(a.ntiles, blockIdx.x / PER_TILE);
-  if (tb >= a.ntiles) return;
-  const Tile t = a.tiles[tb];
+__device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int part, int2 (*rng)[MAX_RANGES]) {
   const CellDev& C = a.cells[t.cell];
-  if (!C.rebuild) return;
-  const int slot = (blockIdx.x % PER_TILE) * BUILD_ATOMS + threadIdx.x / LPA, lane = threadIdx.x % LPA;
+  const int slot = part * BUILD_ATOMS + threadIdx.x / LPA, lane = threadIdx.x % LPA;
   const bool active = slot < t.count;
   const long long i = (long long)t.begin + (active ? slot : 0);
   const int li = (int)(i - C.off);
@@ -1528,6 +1627,27 @@ __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a) {
       n = a.maxnb;
     }
     a.nn[i] = n;
+  }
+}
+
+// use_work: block-strided over the tiles of the rebuild work list; else one block per tile of the
+// batch, exiting at once for cells that do not rebuild
+template <class P, class LT>
+__global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a, int use_work) {
+  constexpr int PER_TILE = TILE / BUILD_ATOMS;
+  __shared__ int2 rng[BUILD_ATOMS][MAX_RANGES];   // candidate ranges (first position, count) per atom
+  if (use_work) {
+    const int n = a.work_count[1] * PER_TILE;
+    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+      __syncthreads();                           // the previous tile's ranges have been read
+      build_tile<P, LT>(a, a.tiles[work_tile(a, k / PER_TILE)], k % PER_TILE, rng);
+    }
+  } else {
+    const int tb = block_tile(a.ntiles, blockIdx.x / PER_TILE);
+    if (tb >= a.ntiles) return;
+    const Tile t = a.tiles[tb];
+    if (!a.cells[t.cell].rebuild) return;
+    build_tile<P, LT>(a, t, blockIdx.x % PER_TILE, rng);
   }
 }
 
@@ -1645,7 +1765,9 @@ __device__ inline void set_box_fields(CellDev& C, double rcs) {
 // left out of the list (|d_build| >= rc + skin) is now at least sigma_min(A) (rc + skin) - 2 u
 // apart, and sigma_min(A) >= 1 - |A - I|_F.  The list therefore still holds every pair within rc
 // while u <= ((1 - |A - I|_F)(rc + skin) - rc) / 2; that bound becomes the cell's displacement
-// threshold, and a rebuild is forced only when it is not positive.
+// threshold.  A rebuild is forced when it is not positive, or when the displacement the atoms
+// already have exceeds it: the remap x <- dR x leaves the scaled offsets since the build unchanged,
+// so it stretches the last measured displacement by at most |dR|_2 <= 1 + |dR - I|_F.
 __device__ inline float kept_list_threshold(const CellDev& C, double rc, double rcs) {
   const double Hb[9] = {C.Hb[0], C.Hb[1], C.Hb[2], 0.0, C.Hb[3], C.Hb[4], 0.0, 0.0, C.Hb[5]};
   double Hbi[9], A[9];
@@ -1673,7 +1795,14 @@ __global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double 
   for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
   C.wcount = 0;
   const float hs2 = kept_list_threshold(C, rc, rcs);
-  if (force_build || C.rebuild || !(hs2 > 0.0f)) {
+  double e2 = 0.0;
+  for (int k = 0; k < 9; ++k) {
+    const double d = S.dR[k] - ((k % 4 == 0) ? 1.0 : 0.0);
+    e2 += d * d;
+  }
+  const double grow = 1.0 + sqrt(e2);
+  const bool moved = (double)C.dmax2 * grow * grow >= (double)hs2;
+  if (force_build || C.rebuild || !(hs2 > 0.0f) || moved) {
     C.rebuild = 1;
   } else {
     C.hs2 = hs2;

@@ -54,6 +54,8 @@ struct rcell_ctx {
   bool cell_prep = false;         // rebuild preparation by one block per cell (k_cell_prep)
   int *nn = nullptr, *abin = nullptr, *binned = nullptr, *bin_cell = nullptr, *sort_tmp = nullptr;
   int *bcount = nullptr, *bstart = nullptr, *bnum = nullptr, *bfill = nullptr;
+  // rebuild work list (k_rebuild_work): cells, prefix sums of their tiles and chunks, three counts
+  int *work_cells = nullptr, *work_tstart = nullptr, *work_kstart = nullptr, *work_count = nullptr;
   CellDev* cells = nullptr;
   Tile* tiles = nullptr;
   Part* parts = nullptr;
@@ -183,6 +185,8 @@ MDArgs make_args(const rcell_ctx* c) {
   a.binned = c->binned;
   a.sort_tmp = c->sort_tmp;
   a.bins_total = c->bins_total;
+  a.work_cells = c->work_cells; a.work_tstart = c->work_tstart; a.work_kstart = c->work_kstart;
+  a.work_count = c->work_count;
   const rcell_params& p = c->p;
   // integrator constants: the same expressions, in the same order, as the method's definition
   a.dt = p.dt;
@@ -294,6 +298,10 @@ void launch_reduce(rcell_ctx* c, int mode) {
   hipLaunchKernelGGL(k_reduce, dim3(c->ncells), dim3(RED_NT), 0, c->stream, a, mode);
 }
 
+// blocks of the block-strided rebuild phases: enough to fill the GPU when many cells rebuild,
+// few enough that a step without rebuilds costs little
+constexpr int WORK_BLOCKS = 2048;
+
 // reduce_mode >= 0: the per-cell reduction of that mode runs first, fused into the preparation
 // launch when the cells are small enough for it
 void launch_build(rcell_ctx* c, int reduce_mode = -1) {
@@ -308,25 +316,34 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
       else hipLaunchKernelGGL(k_cell_prep<Mixed>, gc, bc, 0, c->stream, a);
     }
   } else {
+    // the phases walk the work list of the cells that rebuild: small grids, block-strided
     if (reduce_mode >= 0) launch_reduce(c, reduce_mode);
-    if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gt, bt, 0, c->stream, a);
-    else hipLaunchKernelGGL(k_bin<Mixed>, gt, bt, 0, c->stream, a);
-    hipLaunchKernelGGL(k_bin_scan, gc, bc, 0, c->stream, a);
-    hipLaunchKernelGGL(k_bin_fill, gt, bt, 0, c->stream, a);
-    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((c->bins_total + 63) / 64)), dim3(64),
-                       sizeof(int) * c->sort_cap, c->stream, a, (const int*)c->bin_cell, c->sort_cap);
+    hipLaunchKernelGGL(k_rebuild_work, dim3(1), dim3(SCAN_NT), 0, c->stream, a);
+    const dim3 gw(std::max(1, std::min(WORK_BLOCKS, (c->ntiles + WORK_WAVES - 1) / WORK_WAVES))),
+        bw(TILE * WORK_WAVES);
+    const dim3 gs(std::max(1, std::min(c->ncells, WORK_BLOCKS / 8)));
+    const dim3 gk((unsigned)std::max<long long>(1, std::min<long long>(4 * WORK_BLOCKS, c->bins_total / 64)));
+    if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gw, bw, 0, c->stream, a);
+    else hipLaunchKernelGGL(k_bin<Mixed>, gw, bw, 0, c->stream, a);
+    hipLaunchKernelGGL(k_bin_scan, gs, bc, 0, c->stream, a);
+    hipLaunchKernelGGL(k_bin_fill, gw, bw, 0, c->stream, a);
+    hipLaunchKernelGGL(k_bin_sort, gk, dim3(64), sizeof(int) * c->sort_cap, c->stream, a,
+                       (const int*)c->bin_cell, c->sort_cap);
     if (c->fp64) {
-      hipLaunchKernelGGL(k_reorder_gather<FP64>, gt, bt, 0, c->stream, a);
-      hipLaunchKernelGGL(k_reorder_scatter<FP64>, gt, bt, 0, c->stream, a);
+      hipLaunchKernelGGL(k_reorder_gather<FP64>, gw, bw, 0, c->stream, a);
+      hipLaunchKernelGGL(k_reorder_scatter<FP64>, gw, bw, 0, c->stream, a);
     } else {
-      hipLaunchKernelGGL(k_reorder_gather<Mixed>, gt, bt, 0, c->stream, a);
-      hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gt, bt, 0, c->stream, a);
+      hipLaunchKernelGGL(k_reorder_gather<Mixed>, gw, bw, 0, c->stream, a);
+      hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gw, bw, 0, c->stream, a);
     }
   }
-  const dim3 gl(tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)), bl(BUILD_ATOMS * LPA);
-  if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a);
-  else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a);
-  else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a);
+  const int use_work = c->cell_prep ? 0 : 1;
+  const dim3 gl(use_work ? std::max(1, std::min(WORK_BLOCKS, c->ntiles * (TILE / BUILD_ATOMS)))
+                         : tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)),
+      bl(BUILD_ATOMS * LPA);
+  if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a, use_work);
+  else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a, use_work);
+  else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a, use_work);
 }
 
 void launch_start(rcell_ctx* c) {
@@ -398,7 +415,8 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
   long long total = 0;
   std::vector<int> off(c->ncells), cap(c->ncells);
   for (int k = 0; k < c->ncells; ++k) {
-    cap[k] = std::max(need[k], c->bin_cap.empty() ? 0 : c->bin_cap[k]);
+    // whole 64-bin chunks per cell: the bin sort works on chunks of one cell each
+    cap[k] = (std::max(need[k], c->bin_cap.empty() ? 0 : c->bin_cap[k]) + 63) / 64 * 64;
     off[k] = (int)total;
     total += cap[k];
   }
@@ -585,7 +603,9 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
       (e = dalloc(c, &c->abin, N)) || (e = dalloc(c, &c->binned, N)) || (e = dalloc(c, &c->sort_tmp, N)) ||
       (e = dalloc(c, &c->cells, ncells)) || (e = dalloc(c, &c->tiles, ntiles)) || (e = dalloc(c, &c->parts, ntiles)) ||
       (e = dalloc(c, &c->stage, ncells)) || (e = dalloc(c, &c->dscratch, (size_t)17 * ncells)) || (e = dalloc(c, &c->dscratch2, (size_t)6 * ncells)) ||
-      (e = dalloc(c, &c->iscratch, (size_t)2 * ncells)) || (e = dalloc(c, &c->lscratch, (size_t)2 * ncells)))
+      (e = dalloc(c, &c->iscratch, (size_t)2 * ncells)) || (e = dalloc(c, &c->lscratch, (size_t)2 * ncells)) ||
+      (e = dalloc(c, &c->work_cells, ncells)) || (e = dalloc(c, &c->work_tstart, ncells + 1)) ||
+      (e = dalloc(c, &c->work_kstart, ncells + 1)) || (e = dalloc(c, &c->work_count, 4)))
     return bail(e);
   c->fx = f0; c->fy = f0 + fsz * N; c->fz = f0 + 2 * fsz * N;
   c->s[0] = s0; c->s[1] = s1; c->sb = sbp;

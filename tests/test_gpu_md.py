@@ -330,6 +330,40 @@ def test_small_deformations_keep_the_list_exact(rc):
     assert g.rebuilds() - n0 < 2 * nload
 
 
+def test_deformation_rebuilds_when_the_atoms_already_moved_past_the_new_threshold(rc):
+    # A deformation keeps the list only while the skin still covers the affine change plus the
+    # displacement the atoms already have since the last build.  Here a run ends with a largest
+    # displacement above 0.17 sigma (below skin / 2 = 0.2), and a 5 % stretch lowers the kept-list
+    # threshold to 0.163 sigma: the deformation must rebuild, and the forces of its prime pass must
+    # equal an exact pair enumeration of the remapped state.
+    p = configs.kg_params(precision="mixed")
+    cell = configs.kg_cell([50] * 20, 4100)
+    g = rc.RCellBatch(p, [cell])
+    rcs = p["rc"] + p["skin"]
+    xb = g.get_state(0)["x"]                   # create builds the list at the initial positions
+    nreb = g.rebuilds()
+    u = 0.0
+    for _ in range(400):
+        g.run(1)
+        st = g.get_state(0)
+        if g.rebuilds() != nreb:               # this step rebuilt: the reference is the new state
+            nreb, xb = g.rebuilds(), st["x"]
+            continue
+        u = np.sqrt((min_image(st["x"] - xb, st["H"]) ** 2).sum(1)).max()
+        if u > 0.17:
+            break
+    print("largest displacement since the last build", u, flush=True)
+    assert 0.17 < u < 0.5 * p["skin"]
+    F = np.diag([1.04, 0.98, 0.98])
+    e = np.linalg.norm(F - np.eye(3))
+    assert 0.5 * ((1.0 - e) * rcs - p["rc"]) < u
+    g.set_deformation(F[None])
+    assert g.rebuilds() == nreb + 1
+    st = g.get_state(0)
+    fo = core.forces(p, st["H"], st["x"], cell["bonds"])[0]
+    check_forces(g.get_forces(0), fo, TOL["mixed"], "prime after the deformation")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_rebuild_preparation_paths_are_bitwise_equal(rc, prec):
     # one block per cell (the default for small cells) and the six phase kernels order the bins and
