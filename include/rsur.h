@@ -56,6 +56,16 @@ int rsur_fit_norm(rsur_ctx* ctx, const void* X_dev, const void* Y_dev, int32_t n
  * variance over members of the de-normalised outputs (B x dout FP32 each; var_dev may be NULL).
  * Enqueued only. */
 int rsur_forward(rsur_ctx* ctx, const void* X_dev, int32_t B, void* mean_dev, void* var_dev);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same ensemble mean and variance as rsur_forward,
+ * bit for bit, computed without any allocation.  The members' outputs go to a fixed device array of
+ * 2^21 floats (8 MiB) that the library holds on each device it runs on until the process ends,
+ * instead of the context's activation buffers, so B is limited by that array, not by max_batch:
+ * 1 <= B and K * pad64(B) * pad64(dout) <= 2^21 (4096 rows for K = 8 and dout <= 64), else
+ * RCELL_ERR_ARG.  Needs padded widths <= 256 and at most 8 layers (RCELL_ERR_ARG otherwise).  Every
+ * call on one device shares that device's array: calls that overlap on one device (other streams,
+ * other contexts, other host threads) race and must be serialised by the caller.  Enqueued only. */
+int rsur_forward_static(rsur_ctx* ctx, const void* X_dev, int32_t B, void* mean_dev, void* var_dev);
 /* every member's de-normalised output, K x B x dout FP32 (checks and diagnostics) */
 int rsur_forward_members(rsur_ctx* ctx, const void* X_dev, int32_t B, void* out_dev);
 

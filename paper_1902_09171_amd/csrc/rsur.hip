@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,6 +19,36 @@ using namespace rsur;
 namespace {
 thread_local std::string g_rsur_create_error;
 }
+
+// Scratch of rsur_forward_static: every member's output for the rows of one call (K x pad64(B) x
+// padded dout floats).  One copy per device, holding the last call's outputs until the process
+// ends.  Host code never uses this name as an address: the device address of each device's copy
+// comes from hipGetSymbolAddress (static_scratch_ptr).
+constexpr long long RSUR_STATIC_FLOATS = 1LL << 21;   // 8 MiB
+static __device__ __align__(256) float scratch[RSUR_STATIC_FLOATS];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of the current device's scratch, looked up once per device (no allocation)
+int static_scratch_ptr(float** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return RCELL_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) {
+      (void)hipGetLastError();
+      return RCELL_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = (float*)q;
+  }
+  *out = g_scratch_ptr[dev];
+  return RCELL_OK;
+}
+}  // namespace
 
 struct rsur_ctx {
   int din = 0, width = 0, depth = 0, dout = 0, K = 0, maxB = 0, Mp = 0, L = 0;
@@ -151,6 +182,11 @@ int rsur_create(int32_t din, int32_t width, int32_t depth, int32_t dout, int32_t
     delete c;
     return code;
   };
+  c->err.reserve(256);             // short error messages are then assigned without allocating
+  {
+    float* sp = nullptr;             // the static scratch's address on this device, once per device
+    if (static_scratch_ptr(&sp) != RCELL_OK) return bail(rfail(c, RCELL_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed"));
+  }
   c->din = din; c->width = width; c->depth = depth; c->dout = dout; c->K = ensemble; c->maxB = max_batch;
   c->Mp = pad64(max_batch);
   c->dims.push_back(din);
@@ -293,13 +329,12 @@ int rsur_fit_norm(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t n) 
 // enough (row block, member) pairs to fill the GPU; small batches run layer by layer, whose
 // per-layer grids spread the same work over more blocks
 constexpr int FUSED_MIN_BLOCKS = 512;
-static void forward_infer(rsur_ctx* c, const float* X, int B, int Mp) {
-  const int dmax = *std::max_element(c->dp.begin(), c->dp.end());
-  if (dmax > FW || c->L > MAXL || (long long)(Mp / 64) * c->K < FUSED_MIN_BLOCKS) {
-    normalise_inputs(c, X, B, Mp);
-    forward_layers(c, Mp);
-    return;
-  }
+static bool fused_shape(const rsur_ctx* c) {
+  return *std::max_element(c->dp.begin(), c->dp.end()) <= FW && c->L <= MAXL;
+}
+
+// the fused forward of every member for Mp rows into out (K x Mp x dp[L], member stride sOut)
+static void forward_fused(rsur_ctx* c, const float* X, int B, int Mp, float* out, long long sOut) {
   if (c->pbt_stale) {
     for (int l = 0; l < c->L; ++l) {
       const long long n = (long long)c->dp[l] * c->dp[l + 1];
@@ -314,8 +349,17 @@ static void forward_infer(rsur_ctx* c, const float* X, int B, int Mp) {
   g.L = c->L;
   for (int l = 0; l <= c->L; ++l) g.dp[l] = c->dp[l];
   for (int l = 0; l < c->L; ++l) { g.woff[l] = c->woff[l]; g.boff[l] = c->boff[l]; }
-  g.out = c->out; g.sOut = (long long)c->Mp * c->dp[c->L]; g.ldo = c->dp[c->L];
+  g.out = out; g.sOut = sOut; g.ldo = c->dp[c->L];
   hipLaunchKernelGGL(k_mlp_forward, dim3(Mp / 64, c->K), dim3(256), 0, c->stream, g);
+}
+
+static void forward_infer(rsur_ctx* c, const float* X, int B, int Mp) {
+  if (!fused_shape(c) || (long long)(Mp / 64) * c->K < FUSED_MIN_BLOCKS) {
+    normalise_inputs(c, X, B, Mp);
+    forward_layers(c, Mp);
+    return;
+  }
+  forward_fused(c, X, B, Mp, c->out, (long long)c->Mp * c->dp[c->L]);
 }
 
 static int forward_common(rsur_ctx* c, const void* X_dev, int32_t B, float* mean, float* var, float* members) {
@@ -333,6 +377,23 @@ static int forward_common(rsur_ctx* c, const void* X_dev, int32_t B, float* mean
 int rsur_forward(rsur_ctx* c, const void* X_dev, int32_t B, void* mean_dev, void* var_dev) {
   if (!c || !X_dev || !mean_dev) return c ? rfail(c, RCELL_ERR_ARG, "NULL pointer") : RCELL_ERR_ARG;
   return forward_common(c, X_dev, B, (float*)mean_dev, (float*)var_dev, nullptr);
+}
+
+int rsur_forward_static(rsur_ctx* c, const void* X_dev, int32_t B, void* mean_dev, void* var_dev) {
+  if (!c || !X_dev || !mean_dev) return c ? rfail(c, RCELL_ERR_ARG, "NULL pointer") : RCELL_ERR_ARG;
+  if (!fused_shape(c)) return rfail(c, RCELL_ERR_ARG, "static forward: padded widths <= 256, <= 8 layers");
+  if (B < 1 || (long long)c->K * pad64(B) * c->dp[c->L] > RSUR_STATIC_FLOATS)
+    return rfail(c, RCELL_ERR_ARG, "static forward: B must be >= 1 and K * pad64(B) * pad64(dout) <= 2^21");
+  float* out = nullptr;
+  if (static_scratch_ptr(&out) != RCELL_OK) return rfail(c, RCELL_ERR_DEVICE, "static scratch address");
+  const int Mp = pad64(B);
+  const long long sOut = (long long)Mp * c->dp[c->L];
+  forward_fused(c, (const float*)X_dev, B, Mp, out, sOut);
+  const long long n = (long long)B * c->dout;
+  hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, out, sOut,
+                     c->dp[c->L], c->K, B, c->dout, c->ymu, c->ysd, (float*)mean_dev, (float*)var_dev, (float*)nullptr);
+  if (hipGetLastError() != hipSuccess) return rfail(c, RCELL_ERR_DEVICE, "static forward: launch failed");
+  return RCELL_OK;
 }
 
 int rsur_forward_members(rsur_ctx* c, const void* X_dev, int32_t B, void* out_dev) {

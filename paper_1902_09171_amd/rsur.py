@@ -11,7 +11,7 @@ from .rcell import OK, RCellError, load as _load_lib
 
 EXPORTS = ["rsur_create", "rsur_destroy", "rsur_last_error", "rsur_num_params", "rsur_set_params",
            "rsur_get_params", "rsur_get_grads", "rsur_set_norm", "rsur_fit_norm", "rsur_forward",
-           "rsur_forward_members", "rsur_train_step"]
+           "rsur_forward_members", "rsur_forward_static", "rsur_train_step"]
 
 _configured = False
 
@@ -27,6 +27,7 @@ def load():
             "rsur_get_params": [vp, i32, vp], "rsur_get_grads": [vp, i32, vp],
             "rsur_set_norm": [vp, vp, vp, vp, vp], "rsur_fit_norm": [vp, vp, vp, i32],
             "rsur_forward": [vp, vp, i32, vp, vp], "rsur_forward_members": [vp, vp, i32, vp],
+            "rsur_forward_static": [vp, vp, i32, vp, vp],
             "rsur_train_step": [vp, vp, vp, i32, f32, vp],
         }
         for name, args in sig.items():
@@ -101,6 +102,10 @@ class Surrogate:
 
     def forward(self, X_dev_ptr, B, mean_dev_ptr, var_dev_ptr=None):
         self._check(load().rsur_forward(self._h, X_dev_ptr, int(B), mean_dev_ptr, var_dev_ptr))
+
+    def forward_static(self, X_dev_ptr, B, mean_dev_ptr, var_dev_ptr=None):
+        """rsur_forward_static: the ensemble forward without any device allocation (fixed array)."""
+        self._check(load().rsur_forward_static(self._h, X_dev_ptr, int(B), mean_dev_ptr, var_dev_ptr))
 
     def forward_members(self, X_dev_ptr, B, out_dev_ptr):
         self._check(load().rsur_forward_members(self._h, X_dev_ptr, int(B), out_dev_ptr))
