@@ -73,7 +73,7 @@ ORACLE_SECONDS = 10.0     # CPU time the oracle baseline runs for (bounded sampl
 DEFAULTS = {"cu_element": (50, 3), "cu_batched": (10, 2), "kg_single": (1000, 100), "kg_batched": (10, 1),
             "kg_glassy": (10, 1),
             "fe_bar": (10, 2), "fe_tet": (4, 1), "fe_scaling": (3, 1), "glassy_rates": (4000, 100),
-            "surrogate": (200, 20)}
+            "surrogate": (200, 20), "fe_bar_surrogate": (1, 0)}
 
 
 def kernel_source_hash():
@@ -652,11 +652,159 @@ def bench_surrogate(args, torch, rcell, configs):
     return out
 
 
+SUR_CHAINS = 40                   # chains of 100 beads per training r-cell
+
+
+def _sur_melt(c):
+    from synth import configs
+    from synth.rng import cell_seed
+    return configs.kg_cell([100] * SUR_CHAINS, cell_seed(1902 + 31, c))
+
+
+def bench_fe_bar_surrogate(args, torch, rcell, configs):
+    """The FE bar of fe_bar driven by the learned stress surrogate (153 -> 4 x 256 -> 6, ensemble of
+    5), with batched MD as its fallback:
+      (1) training data from MD-driven bars of the same mesh stepped in lockstep in one batched
+          r-cell context (2000-bead cells, 500 MD steps per load step, other imperfections and pull
+          rates), one (history, sigma_MD) pair per Gauss point per load step;
+      (2) the ensemble trained by the library's BF16 kernels; the OOD threshold is the 99th
+          percentile of the ensemble spread on held-out bars;
+      (3) the bar of 256 r-cells of 40 000 beads driven by the surrogate for the evaluation load
+          steps, while two shadow MD batches of the same cells (two Langevin seeds) follow its
+          deformation: the surrogate's stress error per Gauss point and load step against shadow MD
+          beside the seed-to-seed spread, the fallback fraction, and the time per load step against
+          the MD load step.  The value (ensemble evaluations per second at the bar's 256 Gauss
+          points) is reported only when the error bound holds."""
+    import numpy as np
+    from paper_1902_09171_amd import fe, rsur, surrogate as SU
+    from synth.rng import generator
+    from synth.surrogate import init_params
+    global SUR_CHAINS
+    MD, WARM, NGP = 500, 2000, 256
+    params = configs.kg_params(precision="mixed")
+    NB, NDIST, NLOAD, NEVAL = args.sur_bars, args.sur_melts, args.sur_load, args.sur_eval_load
+    SUR_CHAINS = args.sur_chains
+    NBEAD = 100 * SUR_CHAINS
+    # stress-magnitude floor of the error measure: the thermal pressure scale rho k_B T of the melt;
+    # below it the window stress of one r-cell is dominated by its own fluctuations
+    S_FLOOR = 0.85 * params["kB"] * params["temperature"]
+    rng = generator(1902 + 32, 0)
+    log(f"generating {NDIST} training melts of {SUR_CHAINS} x 100 beads")
+    melts = make_cells(_sur_melt, list(range(NDIST)))
+    meshes, cells, rates = [], [], []
+    for b in range(NB):
+        meshes.append(fe.Hex8Bar(nel=(8, 2, 2), size=(200.0, 50.0, 50.0), rho0=0.85,
+                                 imperfection=float(rng.uniform(0.9, 1.0))))
+        rates.append(float(rng.uniform(0.006, 0.014)))
+        cells.append([melts[(b * NGP + g) % NDIST] for g in range(NGP)])
+    log(f"training data: {NB} bars x {NGP} Gauss points x {NLOAD} load steps of {MD} MD steps")
+    net = rsur.Surrogate(din=SU.FEATURES, width=256, depth=4, dout=6, ensemble=5, max_batch=4096)
+    for k in range(5):
+        net.set_params(k, init_params(net.dims, 41, k))
+    c_wave = fe.md_wave_speed(params, melts[:8], 0.85, MD, warmup_steps=WARM)
+    tr = SU.train_on_bars(torch, net, params, meshes, cells, NLOAD, MD, rates, WARM, args.sur_train_steps,
+                          holdout=max(1, NB // 8), wave_speed=c_wave,
+                          progress=lambda k: (k % 10 == 9) and log(f"  load step {k + 1}/{NLOAD}"))
+    atom_steps_gen = NB * NGP * NBEAD * (WARM + NLOAD * MD)
+    ntrain = int((~tr["held"]).sum())
+    losses = tr["losses"]
+    log(f"  {len(tr['X'])} pairs in {tr['t_gen']:.1f} s ({atom_steps_gen / tr['t_gen']:.3e} atom-steps/s); "
+        f"trained on {ntrain} in {tr['t_train']:.1f} s, loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}")
+
+    # the bar of fe_bar, driven by the surrogate; shadow MD of its own cells follows its deformation
+    log("generating the bar's 256 r-cells of 40 000 beads")
+    bcells = make_cells(_fe_bar_cell, list(range(NGP)))
+    mesh = fe.Hex8Bar(nel=(8, 2, 2), size=(200.0, 50.0, 50.0), rho0=0.85, imperfection=0.95)
+    sur = SU.SurrogateStress(torch, net, tr["y_sd"], tr["tau"], params, bcells, MD, warmup_steps=WARM)
+
+    def progress(k, o):
+        if k % 10 == 9:
+            log(f"  eval load step {k + 1}/{NEVAL}: median error {np.median(o['rel'][-1]):.4f} "
+                f"(MD seed-to-seed {np.median(o['floor'][-1]):.4f}), |sigma| {np.median(o['mags'][-1]):.3f}, "
+                f"flagged {sur.flag_log[-1]}")
+    ev = SU.shadow_evaluation(torch, sur, params, mesh, bcells, MD, NEVAL, 0.01, WARM, S_FLOOR, wave_speed=c_wave,
+                              progress=progress)
+    rel, floor, mags, dev, dev_floor = ev["rel"], ev["floor"], ev["mags"], ev["dev"], ev["dev_floor"]
+    t_sur, t_md, bar = ev["t_provider"], ev["t_md"], ev["bar"]
+    med, flo = np.median(rel, 1), np.median(floor, 1)
+    ok = bool(np.all(med <= 0.05))
+    err_ho = tr["err_ho"]
+    tau = tr["tau"]
+    dt = MD * params["dt"]
+    # ensemble evaluations per second at the bar's batch, device time of the forward calls
+    Xd = torch.tensor(sur.hist.features().astype(np.float32), device="cuda:0")
+    m = torch.zeros((NGP, 6), device="cuda:0")
+    v = torch.zeros_like(m)
+    for _ in range(20):
+        net.forward(Xd.data_ptr(), NGP, m.data_ptr(), v.data_ptr())
+    torch.cuda.synchronize()
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(Xd.data_ptr(), NGP, m.data_ptr(), v.data_ptr())
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / reps
+    if args.dump:
+        np.savez_compressed(args.dump, rel=rel, floor=floor, mags=mags, t_sur=t_sur, t_md=t_md,
+                            flags=np.array(sur.flag_log), err_ho=err_ho, losses=np.array(losses),
+                            spread_ho=tr["spread_ho"], strain=np.array([h["strain"] for h in bar.history]),
+                            dev=dev, dev_floor=dev_floor, tensile=np.array([h["tensile"] for h in bar.history]))
+    value = NGP / t_fwd
+    flagged = float(np.sum(sur.flag_log)) / (NEVAL * NGP)
+    out = {"metric": "surrogate stress-evals/s at <=5% stress error", "value": value if ok else None,
+           "unit": "evals/s", "n_gpus": 1, "steps": NEVAL, "warmup": 0, "ms_per_step": float(np.mean(t_sur)) * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 matrix products, f32 accumulation; MD f32 pair forces, f64 integration/stress",
+           "data": "synthetic",
+           "config": {"workload": "fe_bar_surrogate",
+                      "description": "the fe_bar bar (8x2x2 hex8, 256 Gauss points, r-cells of 400 x 100 beads, "
+                                     "1 % nominal strain and 500 MD steps per load step) driven by the surrogate "
+                                     "153 -> 4 x 256 -> 6, ensemble of 5, batched MD fallback above the OOD "
+                                     "threshold; a step is one FE load step",
+                      "training_pairs": ntrain, "training_bars": NB, "training_cell_beads": NBEAD,
+                      "training_melts": NDIST, "load_steps_per_bar": NLOAD, "md_steps_per_load_step": MD,
+                      "warmup_md_steps": WARM, "eval_load_steps": NEVAL},
+           "error_gate": {"held": ok, "rule": "at every load step, the median over the 256 Gauss points of "
+                                              "|sigma_sur - sigma_MD|_F / max(|sigma_MD|_F, rho kB T) <= 0.05, "
+                                              "sigma_MD from shadow MD of the same cells following the surrogate "
+                                              "bar's deformation; rho kB T = 0.85 eps/sigma^3",
+                          "stress_floor": S_FLOOR,
+                          "median_per_load_step_max": float(med.max()), "median_per_load_step_mean": float(med.mean()),
+                          "p95_all": float(np.quantile(rel, 0.95)),
+                          "md_seed_to_seed_median_per_load_step_max": float(flo.max()),
+                          "md_seed_to_seed_median_mean": float(flo.mean()),
+                          "deviatoric_median_per_load_step_max": float(np.median(dev, 1).max()),
+                          "deviatoric_md_seed_to_seed_median_max": float(np.median(dev_floor, 1).max()),
+                          "per_load_step": {"strain": [round(float(h["strain"]), 4) for h in bar.history],
+                                            "median": [round(float(v), 5) for v in med],
+                                            "md_seed_to_seed_median": [round(float(v), 5) for v in flo],
+                                            "median_sigma_md": [round(float(v), 4) for v in np.median(mags, 1)]},
+                          "held_out_bars_median_vs_training_cells": float(np.median(err_ho)),
+                          "held_out_bars_p95_vs_training_cells": float(np.quantile(err_ho, 0.95))},
+           "fallback_fraction": flagged, "ood_threshold": tau,
+           "time_per_load_step_s": {"surrogate": float(np.mean(t_sur)), "md": float(np.mean(t_md)),
+                                    "speedup": float(np.mean(t_md) / np.mean(t_sur)),
+                                    "surrogate_median": float(np.median(t_sur)),
+                                    "speedup_median": float(np.median(t_md) / np.median(t_sur))},
+           "ensemble_forward_us_at_256": t_fwd * 1e6,
+           "generation": {"pairs": int(len(tr["X"])), "seconds": tr["t_gen"],
+                          "atom_steps_per_s": atom_steps_gen / tr["t_gen"]},
+           "training": {"steps": args.sur_train_steps, "batch": 4096, "seconds": tr["t_train"],
+                        "loss_first": losses[0][1], "loss_last": losses[-1][1]},
+           "cfl": {"wave_speed": c_wave, "dt_fe": dt, "limit": fe.cfl_limit(mesh, c_wave)},
+           "roofline": {"bound": "mfma", "achieved": 2 * 237312 * 5 * NGP / t_fwd / 1e12, "peak": PEAK_BF16 / 1e12,
+                        "unit": "TFLOP/s", "frac": 2 * 237312 * 5 * NGP / t_fwd / PEAK_BF16, "traffic": None,
+                        "kernel": "ensemble forward at batch 256 (latency bound)", "avg_us": t_fwd * 1e6}}
+    if not ok:
+        out["note"] = "the error bound did not hold: value withheld"
+    return out
+
+
 WORKLOADS = {"cu_element": bench_cu_element, "cu_batched": bench_cu_batched, "kg_single": bench_kg_single,
              "kg_batched": bench_kg_batched, "kg_glassy": bench_kg_glassy,
              "fe_bar": lambda *a: bench_fe(*a, name="fe_bar"), "fe_tet": lambda *a: bench_fe(*a, name="fe_tet"),
              "fe_scaling": lambda *a: bench_fe(*a, name="fe_scaling"), "glassy_rates": bench_glassy_rates,
-             "surrogate": bench_surrogate}
+             "surrogate": bench_surrogate, "fe_bar_surrogate": bench_fe_bar_surrogate}
 
 
 def main():
@@ -675,6 +823,13 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per atom (0 = autotune)")
     ap.add_argument("--skin", type=float, default=None,
                     help="neighbour skin override for the MD workloads (changes speed, never the pairs within rc)")
+    ap.add_argument("--sur-bars", type=int, default=32, help="fe_bar_surrogate: training bars")
+    ap.add_argument("--sur-melts", type=int, default=512, help="fe_bar_surrogate: distinct training melts")
+    ap.add_argument("--sur-load", type=int, default=125, help="fe_bar_surrogate: load steps per training bar")
+    ap.add_argument("--sur-eval-load", type=int, default=100, help="fe_bar_surrogate: evaluated load steps")
+    ap.add_argument("--sur-train-steps", type=int, default=30000, help="fe_bar_surrogate: Adam steps")
+    ap.add_argument("--sur-chains", type=int, default=40, help="fe_bar_surrogate: 100-bead chains per training cell")
+    ap.add_argument("--dump", default=None, help="fe_bar_surrogate: write the per-step errors to this .npz")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()

@@ -48,6 +48,21 @@ class _Mesh:
         lo, hi = self.X[:, axis].min(), self.X[:, axis].max()
         return np.where(np.isclose(self.X[:, axis], hi if side else lo))[0]
 
+    def min_length(self):
+        """Smallest element length for the explicit time-step limit: the shortest edge of a brick,
+        or the smallest altitude (3 V / largest face area) of a tetrahedron."""
+        Xe = self.X[self.conn]                       # (nelem, nodes, 3)
+        if self.conn.shape[1] == 8:
+            edges = [(0, 1), (1, 2), (2, 3), (3, 0), (4, 5), (5, 6), (6, 7), (7, 4),
+                     (0, 4), (1, 5), (2, 6), (3, 7)]
+            return float(min(np.linalg.norm(Xe[:, a] - Xe[:, b], axis=1).min() for a, b in edges))
+        V = np.abs(np.einsum("ei,ei->e", np.cross(Xe[:, 1] - Xe[:, 0], Xe[:, 2] - Xe[:, 0]),
+                             Xe[:, 3] - Xe[:, 0])) / 6.0
+        faces = [(0, 1, 2), (0, 1, 3), (0, 2, 3), (1, 2, 3)]
+        amax = np.max([0.5 * np.linalg.norm(np.cross(Xe[:, b] - Xe[:, a], Xe[:, c] - Xe[:, a]), axis=1)
+                       for a, b, c in faces], axis=0)
+        return float((3.0 * V / amax).min())
+
 
 def _grid_nodes(nel, size, imperfection):
     """Nodes of a structured grid of nx x ny x nz bricks on [0, Lx] x [0, Ly] x [0, Lz]; with
@@ -158,13 +173,54 @@ class Tet4Bar(_Mesh):
         self.volume = self.wdet.sum()
 
 
+CFL_SAFETY = 0.9
+
+
+def cfl_limit(mesh, wave_speed):
+    """Largest stable time step of the explicit central differences: 0.9 h / c with h the smallest
+    element length and c the material's longitudinal wave speed."""
+    return CFL_SAFETY * mesh.min_length() / wave_speed
+
+
+def wave_speed(modulus, rho0):
+    """Longitudinal wave speed c = sqrt(M / rho0) for the P-wave modulus M."""
+    return float(np.sqrt(modulus / rho0))
+
+
+def md_wave_speed(params, cells, rho0, md_steps, delta=0.02, warmup_steps=0):
+    """Wave speed of an r-cell material as the explicit integrator sees it: the P-wave modulus
+    M = d sigma_xx / d eps_xx of the stress the cells return for one load step - the average over
+    md_steps MD steps after a step F = diag(1 +- delta, 1, 1) - by central differences over the
+    given cells (two batches on the GPU, the same initial states and noise for both signs).  The
+    instantaneous affine modulus of a dense repulsive melt is an order of magnitude larger, but it
+    relaxes within a fraction of the window, and the FE update only ever sees window averages."""
+    from .rcell import RCellBatch
+    sxx = []
+    for e in (delta, -delta):
+        g = RCellBatch(params, cells)
+        if warmup_steps:
+            g.run(warmup_steps)
+        g.get_stress()
+        g.set_deformation(np.tile(np.diag([1.0 + e, 1.0, 1.0]), (len(cells), 1, 1)))
+        g.run(md_steps)
+        sxx.append(float(g.get_stress()[:, 0].mean()))
+        g.close()
+    return wave_speed((sxx[0] - sxx[1]) / (2.0 * delta), rho0)
+
+
 class ExplicitBar:
     """Central-difference time stepping of the bar under a constant pull velocity.
 
     provider(F) -> (P, sigma): first Piola-Kirchhoff stress (ngp, 3, 3) and Cauchy stress (ngp, 6)
-    for the deformation gradients F (ngp, 3, 3) of one load step."""
+    for the deformation gradients F (ngp, 3, 3) of one load step.  With wave_speed given, a time
+    step beyond the CFL limit (cfl_limit) is refused with a ValueError."""
 
-    def __init__(self, mesh, provider, dt, pull_velocity, damping=0.0):
+    def __init__(self, mesh, provider, dt, pull_velocity, damping=0.0, wave_speed=None):
+        if wave_speed is not None:
+            lim = cfl_limit(mesh, wave_speed)
+            if not dt <= lim:
+                raise ValueError(f"FE time step {dt:g} exceeds the CFL limit {CFL_SAFETY} h / c = {lim:g} "
+                                 f"(h = {mesh.min_length():g}, c = {wave_speed:g})")
         self.m, self.provider, self.dt, self.vp, self.c = mesh, provider, dt, pull_velocity, damping
         self.u = np.zeros((mesh.nnodes, 3))
         self.v = np.zeros((mesh.nnodes, 3))
@@ -189,8 +245,17 @@ class ExplicitBar:
 
     def step(self):
         """One load step: stresses at the current configuration, then v and u advance by dt."""
-        F = self.m.deformation_gradients(self.u)
+        F = self.begin_step()
         P, sigma = self.provider(F)
+        return self.finish_step(F, P, sigma)
+
+    def begin_step(self):
+        """The deformation gradients of the current configuration (the provider's input)."""
+        return self.m.deformation_gradients(self.u)
+
+    def finish_step(self, F, P, sigma):
+        """Advance v and u by dt under the stresses P of the configuration F (several bars can
+        share one batched stress provider between begin_step and finish_step)."""
         f = -self.m.internal_forces(P)
         a = f / self.m.mass[:, None] - self.c * self.v
         self.v += self.dt * a

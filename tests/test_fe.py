@@ -90,3 +90,34 @@ def test_tetrahedral_mesh_is_conforming():
     P[:, 0, 0] = 1.7
     f = m.internal_forces(P)
     assert f[m.face(0, 1), 0].sum() == pytest.approx(1.7 * 22.7 * 22.7, rel=1e-12)
+
+
+@pytest.mark.parametrize("mesh", MESHES)
+def test_cfl_check(mesh):
+    """The explicit step is refused beyond 0.9 h / c: the neo-Hookean P-wave modulus lambda + 2 mu
+    gives c, the smallest element length h (shortest brick edge, smallest tetrahedron altitude)."""
+    m = mesh(nel=(4, 2, 2), size=(40.0, 10.0, 12.0))
+    mu, lam, rho0 = 1.3, 2.1, m.rho0
+    c = fe.wave_speed(lam + 2.0 * mu, rho0)
+    assert c == pytest.approx(np.sqrt((lam + 2 * mu) / rho0), rel=1e-15)
+    h = m.min_length()
+    if mesh is fe.Hex8Bar:
+        assert h == pytest.approx(5.0)                  # 10 / 2, the shortest brick edge
+    else:
+        assert 0.0 < h < 5.0                            # altitudes are shorter than the brick edges
+    lim = fe.cfl_limit(m, c)
+    assert lim == pytest.approx(0.9 * h / c)
+    fe.ExplicitBar(m, fe.neo_hookean(mu, lam), dt=0.99 * lim, pull_velocity=0.01, wave_speed=c)
+    with pytest.raises(ValueError, match="CFL"):
+        fe.ExplicitBar(m, fe.neo_hookean(mu, lam), dt=1.01 * lim, pull_velocity=0.01, wave_speed=c)
+
+
+def test_tet_altitude_of_the_unit_corner_tetrahedron():
+    """The corner tetrahedron (0, e_x, e_y, e_z) has volume 1/6 and largest face sqrt(3)/2, so its
+    smallest altitude is 3 (1/6) / (sqrt(3)/2) = 1/sqrt(3)."""
+    class One(fe._Mesh):
+        pass
+    m = One()
+    m.X = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    m.conn = np.array([[0, 1, 2, 3]])
+    assert m.min_length() == pytest.approx(1.0 / np.sqrt(3.0), rel=1e-14)

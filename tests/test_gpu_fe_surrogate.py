@@ -1,25 +1,38 @@
-"""End to end on the GPU: training data from batched MD r-cells, the BF16 ensemble trained by the
-library's own kernels, its error against MD next to the MD seed-to-seed spread, the
-out-of-distribution check with MD fallback, and the FE bar driven by MD and by the surrogate
-(stress within 5 % of the MD-driven run, and the speed-up).
+"""End to end on the GPU at a miniature scale: training data from MD-driven FE bars stepped in
+lockstep in one batched r-cell context, the configured ensemble (153 -> 4 x 256 -> 6, K = 5) trained
+by the library's own kernels, the out-of-distribution check with MD fallback, and a bar driven by
+the surrogate while two shadow MD batches of its cells follow its deformation.
 
-The bar's stress error is read over the whole run (sum over load steps of the deviation of the
-Gauss-point mean stress, divided by the sum of its magnitude): with free lateral faces the melt's
-initial pressure relaxes towards zero stress, so a per-step ratio would divide by near-zero values."""
-import time
-
+The error measure is that of the full-size benchmark (bench.py --workload fe_bar_surrogate): per load
+step, the median over the Gauss points of |sigma_sur - sigma_MD|_F / max(|sigma_MD|_F, rho kB T),
+with rho kB T = 0.85 eps/sigma^3 the melt's thermal pressure scale (the bar's stress relaxes far below
+it).  The full-size bar, whose 40 000-bead cells differ from seed to seed by at most ~1.3 % on this
+measure, is held to 5 %.  The miniature's 4000-bead cells differ by up to ~4 % from seed to seed, so
+here the bound is max(5 %, 1.5 x the MD seed-to-seed spread of the same load step).  What is
+miniature: a bar of 4 x 1 x 1 hex8 elements (32 Gauss points) instead of 8 x 2 x 2 (256), r-cells of
+40 x 100 beads instead of 400 x 100, 30 training bars of 40 load steps (~3.8e4 pairs) instead of 28
+of 125 (~9e5); the network is the configured one."""
 import numpy as np
 import pytest
 
-from synth import configs, stretch_paths
-from synth.rng import generator
+from synth import configs
+from synth.rng import cell_seed, generator
 from synth.surrogate import init_params
 
 pytestmark = pytest.mark.gpu
 
-MD_STEPS = 100         # MD steps per load step (0.5 tau)
-NLOAD = 30
-BAR = dict(nel=(4, 1, 1), size=(40.0, 10.0, 10.0), rho0=0.85)
+MD_STEPS = 500              # MD steps per load step, as in the full-size bar
+WARM = 1000
+NLOAD = 40
+BARS = 32                   # the last two are held out
+MINI = dict(nel=(4, 1, 1), size=(160.0, 40.0, 40.0), rho0=0.85)   # 40-sigma elements
+FLOOR = 0.85                # rho kB T
+BOUND = 0.05
+SPREAD_FACTOR = 1.5
+
+
+def melt(k):
+    return configs.kg_cell([100] * 40, cell_seed(4711, k))
 
 
 @pytest.fixture(scope="module")
@@ -27,63 +40,37 @@ def trained():
     import torch
     from paper_1902_09171_amd import fe, rsur, surrogate as SU
     params = configs.kg_params(precision="mixed")
-    # (1) random rotation-free stretch paths, lateral contraction or expansion
-    cells = [configs.kg_cell([50] * 20, 500 + k) for k in range(96)]
-    paths = stretch_paths(96, NLOAD, generator(77, 0), rate_max=0.01, nu=(-0.6, 0.5))
-    Xa, Ya = SU.generate_data(torch, params, cells, paths, MD_STEPS, warmup_steps=600)
-    # (2) MD-driven bars of the kind the surrogate will drive (other imperfections, rates, seeds)
-    Xb, Yb = [], []
-    for v, (imp, rate) in enumerate(((0.96, 0.004), (1.0, 0.006))):
-        mesh = fe.Hex8Bar(imperfection=imp, **BAR)
-        bcells = [configs.kg_cell([50] * 20, 20000 + 100 * v + g) for g in range(mesh.ngp)]
-        x, y, _ = SU.generate_bar_data(torch, dict(params, seed=100 + v), mesh, bcells, 20, MD_STEPS, rate,
-                                       warmup_steps=600)
-        Xb.append(x); Yb.append(y)
-    ntr = 80 * NLOAD                                # the last 16 stretch paths are held out
-    X = np.concatenate([Xa[:ntr]] + Xb + [Xa[ntr:]])
-    Y = np.concatenate([Ya[:ntr]] + Yb + [Ya[ntr:]])
-    ntr = len(X) - len(Xa[80 * NLOAD:])
-    net = rsur.Surrogate(din=SU.FEATURES, width=128, depth=3, dout=6, ensemble=5, max_batch=1024)
+    rng = generator(4712, 0)
+    meshes, cells, rates = [], [], []
+    for b in range(BARS):
+        meshes.append(fe.Hex8Bar(imperfection=float(rng.uniform(0.9, 1.0)), **MINI))
+        rates.append(float(rng.uniform(0.006, 0.014)))
+        cells.append([melt(b * 32 + g) for g in range(32)])
+    net = rsur.Surrogate(din=SU.FEATURES, width=256, depth=4, dout=6, ensemble=5, max_batch=4096)
     for k in range(5):
         net.set_params(k, init_params(net.dims, 31, k))
-    log = SU.train(torch, net, X[:ntr], Y[:ntr], steps=6000, batch=1024, lr=4e-3, lr_final=4e-4, log_every=1000)
-    y_sd = Y[:ntr].std(0)
-    mean, var = SU.predict(torch, net, X[ntr:])
-    tau = float(np.quantile(SU.spread(var, y_sd), 0.99))
-    # MD seed-to-seed spread: the held-out paths again from different initial states and noise
-    cells2 = [configs.kg_cell([50] * 20, 9000 + k) for k in range(16)]
-    _, Y2 = SU.generate_data(torch, dict(params, seed=4242), cells2, paths[80:], MD_STEPS, warmup_steps=600)
-    return dict(torch=torch, SU=SU, net=net, params=params, X=X, Y=Y, ntr=ntr, mean=mean, var=var, tau=tau,
-                y_sd=y_sd, Y2=Y2, log=log, paths=paths)
+    c = fe.md_wave_speed(params, [melt(5000 + k) for k in range(4)], 0.85, MD_STEPS, warmup_steps=WARM)
+    tr = SU.train_on_bars(torch, net, params, meshes, cells, NLOAD, MD_STEPS, rates, WARM, 2000, holdout=2,
+                          batch=2048, lr=2e-3, lr_final=2e-4, wave_speed=c)
+    print(f"{len(tr['X'])} pairs, loss {tr['losses'][0][1]:.3f} -> {tr['losses'][-1][1]:.3f}, tau {tr['tau']:.3f}",
+          flush=True)
+    return dict(torch=torch, SU=SU, fe=fe, net=net, params=params, c=c, **tr)
 
 
-def rel_err(a, b):
-    fro = lambda s: np.sqrt((s[:, :3] ** 2).sum(1) + 2 * (s[:, 3:] ** 2).sum(1))
-    return fro(a - b) / fro(b)
-
-
-def test_surrogate_error_against_md_and_noise_floor(trained):
-    t = trained
-    assert t["log"][-1][1] < 0.5 * t["log"][0][1]
-    Yh = t["Y"][t["ntr"]:]
-    err = rel_err(t["mean"], Yh)
-    noise = rel_err(t["Y2"], Yh)
-    print(f"held-out surrogate error median {np.median(err):.4f} p95 {np.quantile(err, 0.95):.4f}; "
-          f"MD seed-to-seed median {np.median(noise):.4f}", flush=True)
-    # the 5 % target is read against the MD noise floor of the same cells and windows
-    assert np.median(err) <= max(0.05, 1.2 * np.median(noise))
+def test_training_reduces_the_loss(trained):
+    assert trained["losses"][-1][1] < 0.8 * trained["losses"][0][1]
 
 
 def test_ood_flag_and_md_fallback(trained):
     t = trained
     torch, SU = t["torch"], t["SU"]
-    far = t["X"][t["ntr"]:t["ntr"] + 4].copy()
+    far = t["X"][t["held"]][:4].copy()
     far[:, :9] = np.array([1.0, 0.35, 0.2, 0, 1.0, 0.0, 0, 0, 1.0])   # a shear far beyond the training data
     _, var = SU.predict(torch, t["net"], far)
     assert np.all(SU.spread(var, t["y_sd"]) > t["tau"])
     # the provider routes flagged points to MD r-cells (replaying their history) and the rest to the net
-    cells = [configs.kg_cell([50] * 20, 700 + k) for k in range(4)]
-    prov = SU.SurrogateStress(torch, t["net"], t["y_sd"], t["tau"], t["params"], cells, MD_STEPS)
+    cells = [melt(900 + k) for k in range(4)]
+    prov = SU.SurrogateStress(torch, t["net"], t["y_sd"], t["tau"], t["params"], cells, MD_STEPS, warmup_steps=WARM)
     Fs = [np.eye(3)[None].repeat(4, 0) for _ in range(2)]
     Fs.append(np.stack([np.eye(3)] * 3 + [np.array([[1.0, 0.35, 0.2], [0, 1.0, 0], [0, 0, 1.0]])]))
     for F in Fs:
@@ -92,46 +79,20 @@ def test_ood_flag_and_md_fallback(trained):
     assert np.all(np.isfinite(P)) and np.all(np.isfinite(sigma))
 
 
-def test_fe_bar_surrogate_vs_md_gain(trained):
+def test_surrogate_bar_within_bound_of_shadow_md_and_faster(trained):
     t = trained
-    torch, SU = t["torch"], t["SU"]
-    from paper_1902_09171_amd import fe
-    mesh = fe.Hex8Bar(imperfection=0.98, **BAR)
-    dt = MD_STEPS * t["params"]["dt"]
-    vpull = 0.005 * 40.0 / dt                       # 0.5 % nominal strain per load step
-    cells = [configs.kg_cell([50] * 20, 3000 + g) for g in range(mesh.ngp)]
-
-    def run(provider, nsteps):
-        bar = fe.ExplicitBar(mesh, provider, dt=dt, pull_velocity=vpull, damping=0.2)
-        t0 = time.perf_counter()
-        for _ in range(nsteps):
-            bar.step()
-        return bar, (time.perf_counter() - t0) / nsteps
-
-    # warm the MD cells as in training, then compare the two drivers over the same load steps;
-    # a second MD-driven bar from other initial states and noise gives the MD noise floor
-    md = fe.MDStress(t["params"], cells, MD_STEPS)
-    md.g.run(600)
-    bar_md, t_md = run(md, 20)
-    cells_b = [configs.kg_cell([50] * 20, 6000 + g) for g in range(mesh.ngp)]
-    md_b = fe.MDStress(dict(t["params"], seed=999), cells_b, MD_STEPS)
-    md_b.g.run(600)
-    bar_md2, _ = run(md_b, 20)
-    sur = SU.SurrogateStress(torch, t["net"], t["y_sd"], t["tau"], t["params"], cells, MD_STEPS)
-    bar_s, t_s = run(sur, 20)
-
-    def mean_stress(bar):                           # Gauss-point average of sigma_FEM per load step
-        return np.array([h["sigma"].mean(0) for h in bar.history])
-
-    fro = lambda s: np.sqrt((s[:, :3] ** 2).sum(1) + 2 * (s[:, 3:] ** 2).sum(1))
-    ref = mean_stress(bar_md)
-    dev = float(fro(mean_stress(bar_s) - ref).sum() / fro(ref).sum())
-    floor = float(fro(mean_stress(bar_md2) - ref).sum() / fro(ref).sum())
+    torch, SU, fe = t["torch"], t["SU"], t["fe"]
+    mesh = fe.Hex8Bar(imperfection=0.95, **MINI)
+    cells = [melt(1000 + g) for g in range(mesh.ngp)]
+    sur = SU.SurrogateStress(torch, t["net"], t["y_sd"], t["tau"], t["params"], cells, MD_STEPS, warmup_steps=WARM)
+    ev = SU.shadow_evaluation(torch, sur, t["params"], mesh, cells, MD_STEPS, 30, 0.01, WARM, FLOOR, wave_speed=t["c"])
+    med, flo = np.median(ev["rel"], 1), np.median(ev["floor"], 1)
     flagged = sum(sur.flag_log) / (len(sur.flag_log) * mesh.ngp)
-    print(f"FE bar: mean-stress deviation surrogate {dev:.4f} vs MD seed-to-seed {floor:.4f}; flagged "
-          f"fraction {flagged:.3f}; time per load step MD {t_md * 1e3:.1f} ms, surrogate {t_s * 1e3:.1f} ms "
-          f"(gain {t_md / t_s:.1f}x)", flush=True)
-    assert dev <= max(0.05, 1.5 * floor)
-    assert flagged < 0.2
-    if flagged < 0.1:
-        assert t_s < t_md
+    t_sur, t_md = float(np.median(ev["t_provider"])), float(np.median(ev["t_md"]))
+    print("per load step median error", np.round(med, 4), flush=True)
+    print("MD seed-to-seed            ", np.round(flo, 4), flush=True)
+    print(f"flagged fraction {flagged:.3f}; time per load step: surrogate {t_sur * 1e3:.2f} ms, MD {t_md * 1e3:.1f} ms",
+          flush=True)
+    assert np.all(med <= np.maximum(BOUND, SPREAD_FACTOR * flo))
+    assert flagged < 0.1
+    assert t_sur < t_md
