@@ -8,12 +8,14 @@
 //               Differences of two such integers wrap modulo 2^32 (2^64), which is exactly the
 //               per-component minimum image in scaled space: the pair separation needs no
 //               image shifts (d = H dS, formed in FP64 and rounded once in mixed precision).
-//   sb          s at the last neighbour build (displacement check)
+//   sb          s at the last neighbour build, quantised to its top 16 bits per component (8 bytes;
+//               the displacement check allows for the quantisation, see qeps)
 //   nbr         Verlet list within rc + skin, cell-local j, as 16-bit indices when every cell has
 //               at most 65536 atoms (mixed precision), else 32-bit; entries of one atom in blocks
 //               of NBLK, the blocks of entries [b NBLK, (b+1) NBLK) of all atoms side by side
 //               (list_index), so a lane loads its UNR entries of a trip with one vector load
-//   bond        up to four FENE partners per atom (cell-local positions, -1 = none)
+//   bond        up to four FENE partners per atom (cell-local positions; the atom's own position marks an
+//               empty slot), 16-bit slots when the list entries are 16-bit, else 32-bit
 //   gid         original cell-local index of the atom stored at each position; pos_of inverts it;
 //               bond0 holds the partners by original index.  At every neighbour build a cell's
 //               atoms are reordered by (bin, original index), so that neighbours sit close in
@@ -63,8 +65,10 @@ struct CellDev {
   int nb[3], bin_off, bin_cap;
   int rebuild, pending, status, pad;
   double Hb[6];                   // H at the last neighbour build, upper triangle (0 1 2 4 5 8)
-  float hs2;                      // squared displacement that still keeps the list complete
-  float dmax2;                    // largest squared displacement since the last build, as last reduced
+  float hs2;                      // squared (measured) displacement that still keeps the list complete
+  float dmax2;                    // largest squared measured displacement since the last build, as last reduced
+  float qeps;                     // bound on the error of a measured displacement: the 16-bit build reference
+  int pad3;
   // molecular statics (FIRE): time step, mixing parameter, the velocity update of this iteration
   // (v = fa v + fb f, or zero when frozen), iterations since the power last turned negative,
   // converged flag and iterations used
@@ -103,9 +107,11 @@ struct Stage {                    // set_deformation staging, one per cell
 struct MDArgs {
   double *x, *y, *z, *vx, *vy, *vz;
   void *fx, *fy, *fz;
-  void *s_cur, *s_nxt, *sb;
-  int4* bond;
+  void *s_cur, *s_nxt;
+  uint2* sb;
+  void* bond;                      // 4 partner slots per atom: uint16_t when bond16, else int
   const int4* bond0;
+  int bond16;
   int* gid;
   int* pos_of;
   char* pscr;                      // reorder scratch: 6 doubles, one S and two ints per atom (npad rows)
@@ -212,6 +218,21 @@ struct Mixed {
   // single hardware instructions (about 1 ulp): ample for FP32 pair forces
   __device__ static R rsq(R x) { return __builtin_amdgcn_rsqf(x); }
   __device__ static R rcp(R x) { return __builtin_amdgcn_rcpf(x); }
+  // the build reference: each fixed-point component rounded to its top 16 bits (x | y << 16, z)
+  __device__ static uint2 quant(const S& s) {
+    const unsigned qx = ((unsigned)s.x + 0x8000u) >> 16, qy = ((unsigned)s.y + 0x8000u) >> 16;
+    const unsigned qz = ((unsigned)s.z + 0x8000u) >> 16;
+    return make_uint2(qx | (qy << 16), qz);
+  }
+  // displacement of sn from a quantised reference (minimum image, like sep)
+  __device__ static void disp(const S& sn, uint2 q, const Geo& g, R d[3]) {
+    const double a = (double)(int)((unsigned)sn.x - ((q.x & 0xffffu) << 16));
+    const double b = (double)(int)((unsigned)sn.y - (q.x & 0xffff0000u));
+    const double c = (double)(int)((unsigned)sn.z - ((q.y & 0xffffu) << 16));
+    d[0] = (float)fma(g.h[0], a, fma(g.h[1], b, g.h[2] * c));
+    d[1] = (float)fma(g.h[3], b, g.h[4] * c);
+    d[2] = (float)(g.h[5] * c);
+  }
 };
 
 struct FP64 {
@@ -259,12 +280,29 @@ struct FP64 {
   }
   __device__ static R rsq(R x) { return 1.0 / sqrt(x); }
   __device__ static R rcp(R x) { return 1.0 / x; }
+  __device__ static uint2 quant(const S& s) {
+    const unsigned long long h = 1ull << 47;
+    const unsigned qx = (unsigned)(((unsigned long long)s.x + h) >> 48);
+    const unsigned qy = (unsigned)(((unsigned long long)s.y + h) >> 48);
+    const unsigned qz = (unsigned)(((unsigned long long)s.z + h) >> 48);
+    return make_uint2(qx | (qy << 16), qz);
+  }
+  __device__ static void disp(const S& sn, uint2 q, const Geo& g, R d[3]) {
+    const double a = cvt((long long)((unsigned long long)sn.x - ((unsigned long long)(q.x & 0xffffu) << 48)));
+    const double b = cvt((long long)((unsigned long long)sn.y - ((unsigned long long)(q.x >> 16) << 48)));
+    const double c = cvt((long long)((unsigned long long)sn.z - ((unsigned long long)(q.y & 0xffffu) << 48)));
+    d[0] = g.h[0] * a + g.h[1] * b + g.h[2] * c;
+    d[1] = g.h[3] * b + g.h[4] * c;
+    d[2] = g.h[5] * c;
+  }
 };
 
 // S = H^-1 x for upper-triangular H^-1, reduced to its fractional part
+// (explicit fused multiply-adds: every caller rounds identically, so the fixed-point coordinates
+// that the Kremer-Grest force pass recomputes from x equal the stored ones bit for bit)
 __device__ __forceinline__ void scaled_frac(const CellDev& C, double x, double y, double z, double f[3]) {
-  const double s0 = C.Hi[0] * x + C.Hi[1] * y + C.Hi[2] * z;
-  const double s1 = C.Hi[4] * y + C.Hi[5] * z;
+  const double s0 = fma(C.Hi[0], x, fma(C.Hi[1], y, C.Hi[2] * z));
+  const double s1 = fma(C.Hi[4], y, C.Hi[5] * z);
   const double s2 = C.Hi[8] * z;
   f[0] = s0 - floor(s0);
   f[1] = s1 - floor(s1);
@@ -398,7 +436,8 @@ struct TailOut {
 
 template <class P>
 __device__ __forceinline__ void atom_tail(const MDArgs& a, const CellDev& C, int cell, long long i,
-                                          double fcx, double fcy, double fcz, int mode, TailOut& o) {
+                                          double fcx, double fcy, double fcz, int mode, TailOut& o,
+                                          const double* xin = nullptr) {
   double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
   const int gid = a.gid[i];
   double f0 = fcx, f1 = fcy, f2 = fcz;
@@ -444,13 +483,14 @@ __device__ __forceinline__ void atom_tail(const MDArgs& a, const CellDev& C, int
     vx += a.h * f0;  // first half kick of the next step
     vy += a.h * f1;
     vz += a.h * f2;
-    const double x = a.x[i] + a.dt * vx, y = a.y[i] + a.dt * vy, z = a.z[i] + a.dt * vz;
+    const double x0 = xin ? xin[0] : a.x[i], y0 = xin ? xin[1] : a.y[i], z0 = xin ? xin[2] : a.z[i];
+    const double x = x0 + a.dt * vx, y = y0 + a.dt * vy, z = z0 + a.dt * vz;
     a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
     a.x[i] = x; a.y[i] = y; a.z[i] = z;
     const typename P::S sn = fixed_pos<P>(C, x, y, z);
     P::store_xyz(a.s_nxt, i, sn);
     typename P::R d[3];
-    P::sep(sn, P::load(a.sb, i), C, d);
+    P::disp(sn, a.sb[i], P::geo(C), d);
     o.maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     if (a.gamma_on) {
       int k[3];
@@ -647,9 +687,13 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   const long long i = (long long)t.begin + slot;
   R f[3] = {0, 0, 0}, pe = 0;
   double w[6] = {0, 0, 0, 0, 0, 0};
+  double xi[3] = {0.0, 0.0, 0.0};
   int status = 0;
   if (active) {
-    const typename P::S si = P::load(a.s_cur, i);
+    // the atom's own fixed-point coordinates are recomputed from its position (they are stored only
+    // for the neighbours' gathers): the position is read here for the drift anyway
+    xi[0] = a.x[i]; xi[1] = a.y[i]; xi[2] = a.z[i];
+    const typename P::S si = fixed_pos<P>(C, xi[0], xi[1], xi[2]);
     const int nn = a.nn[i];
     const R rc2 = (R)a.rc2, sig2 = (R)a.lj_sig2, e24 = (R)(24.0 * a.lj_eps), e4 = (R)(4.0 * a.lj_eps), sh = (R)a.lj_shift;
     const typename P::Geo g = P::geo(C);
@@ -680,12 +724,19 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
     if (mode == MODE_STEP || mode == MODE_DRY) pairs(std::false_type{});
     else pairs(std::true_type{});
     if (lane == 0) {
-      const int4 b = a.bond[i];
-      const int bp[4] = {b.x, b.y, b.z, b.w};
+      const int li = (int)(i - C.off);
+      int bp[4];
+      if constexpr (sizeof(LT) == 2) {
+        const uint2 b = ((const uint2*)a.bond)[i];
+        bp[0] = (int)(b.x & 0xffffu); bp[1] = (int)(b.x >> 16); bp[2] = (int)(b.y & 0xffffu); bp[3] = (int)(b.y >> 16);
+      } else {
+        const int4 b = ((const int4*)a.bond)[i];
+        bp[0] = b.x; bp[1] = b.y; bp[2] = b.z; bp[3] = b.w;
+      }
       const R K = (R)a.fene_K, R02 = (R)a.fene_R02;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (bp[q] < 0) continue;
+        if (bp[q] == li) continue;               // empty slot
         R d[3];
         double dd[3];
         P::sep2(P::load_rel(sc, bp[q]), si, g, d, dd);
@@ -704,7 +755,7 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   for (int q = 0; q < 6; ++q) W[q] = 0.5 * lane_sum<TPA>(w[q]);
   double PE = (double)lane_sum<TPA>(pe);
   const double fc0 = (double)lane_sum<TPA>(f[0]), fc1 = (double)lane_sum<TPA>(f[1]), fc2 = (double)lane_sum<TPA>(f[2]);
-  long long xi[3] = {0, 0, 0};
+  long long nz[3] = {0, 0, 0};
   float maxd2 = 0.f;
   if (lane != 0) {
 #pragma unroll
@@ -713,15 +764,15 @@ __global__ __launch_bounds__(TILE * TPA) void k_force_kg(MDArgs a, int mode) {
   }
   if (active && lane == 0 && mode != MODE_DRY) {
     TailOut o;
-    atom_tail<P>(a, C, t.cell, i, fc0, fc1, fc2, mode, o);
+    atom_tail<P>(a, C, t.cell, i, fc0, fc1, fc2, mode, o, xi);
 #pragma unroll
     for (int q = 0; q < 6; ++q) K[q] = o.K[q];
-    xi[0] = o.xi[0]; xi[1] = o.xi[1]; xi[2] = o.xi[2];
+    nz[0] = o.xi[0]; nz[1] = o.xi[1]; nz[2] = o.xi[2];
     maxd2 = o.maxd2;
   }
   double V[6];
   part_values(a, mode, W, K, V);
-  write_part<NT, TPA>(a.parts, tb, V, PE, mode != MODE_STEP, xi, maxd2, status, psh);
+  write_part<NT, TPA>(a.parts, tb, V, PE, mode != MODE_STEP, nz, maxd2, status, psh);
 }
 
 // Sutton-Chen with n = 9, m = 6 is evaluated in powers of s3 = r^-3: with t = a / r,
@@ -900,7 +951,7 @@ __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
     const typename P::S sn = fixed_pos<P>(C, x, y, z);
     P::store_xyz(a.s_cur, i, sn);
     typename P::R d[3];
-    P::sep(sn, P::load(a.sb, i), C, d);
+    P::disp(sn, a.sb[i], P::geo(C), d);
     maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     if (a.gamma_on) {
       int k[3];
@@ -962,7 +1013,7 @@ __global__ __launch_bounds__(TILE) void k_fire_move(MDArgs a) {
     const typename P::S sn = fixed_pos<P>(C, x, y, z);
     P::store_xyz(a.s_cur, i, sn);
     typename P::R d[3];
-    P::sep(sn, P::load(a.sb, i), C, d);
+    P::disp(sn, a.sb[i], P::geo(C), d);
     maxd2 = (float)(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   }
   const double Z[6] = {0, 0, 0, 0, 0, 0};
@@ -1143,7 +1194,7 @@ __device__ __forceinline__ void bin_atom(const MDArgs& a, const CellDev& C, long
   scaled_frac(C, x, y, z, f);
   const typename P::S sv = P::make(f[0], f[1], f[2]);
   P::store_xyz(a.s_cur, i, sv);
-  P::store_xyz(a.sb, i, sv);
+  a.sb[i] = P::quant(sv);
   int b[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) b[q] = min((int)(f[q] * C.nb[q]), C.nb[q] - 1);
@@ -1185,6 +1236,14 @@ __global__ __launch_bounds__(TILE * WORK_WAVES) void k_bin(MDArgs a) {
   for_work_tiles(a, [&](const Tile& t, long long i) { bin_atom<P>(a, a.cells[t.cell], i); });
 }
 
+// The displacement threshold for displacements measured against the 16-bit build reference: a
+// measured displacement is within qeps of the true one, so the list stays complete while the
+// measured one is at most the true bound (squared: hs2) minus qeps.
+__device__ __forceinline__ float measured_threshold(double hs2, float qeps) {
+  const double h = sqrt(fmax(hs2, 0.0)) - (double)qeps;
+  return h > 0.0 ? (float)(h * h) : -1.0f;
+}
+
 constexpr int SCAN_NT = 1024;
 // Exclusive scan of one value per thread over a block of SCAN_NT threads: an inclusive scan inside
 // each wave by shuffles, the 16 wave totals scanned by the first wave through LDS (wsum: 16 ints),
@@ -1222,7 +1281,7 @@ __device__ __forceinline__ void scan_cell(const MDArgs& a, CellDev& C, int* sh) 
   if (t == 0) {                    // the list about to be built holds every pair within rc + skin
     const int up[6] = {0, 1, 2, 4, 5, 8};
     for (int q = 0; q < 6; ++q) C.Hb[q] = C.H[up[q]];
-    C.hs2 = (float)a.half_skin2;
+    C.hs2 = measured_threshold(a.half_skin2, C.qeps);
     C.dmax2 = 0.f;
   }
   int carry = 0;
@@ -1399,6 +1458,14 @@ struct Reorder {
   }
 };
 
+// the four partner slots of the atom at position i (cell-local positions, its own for an empty slot)
+__device__ __forceinline__ void store_bonds(const MDArgs& a, long long i, int b0, int b1, int b2, int b3) {
+  if (a.bond16)
+    ((uint2*)a.bond)[i] = make_uint2((unsigned)b0 | ((unsigned)b1 << 16), (unsigned)b2 | ((unsigned)b3 << 16));
+  else
+    ((int4*)a.bond)[i] = make_int4(b0, b1, b2, b3);
+}
+
 template <class P>
 __device__ __forceinline__ void reorder_gather_atom(const MDArgs& a, const CellDev& C, long long q) {
   const long long src = C.off + a.binned[q];
@@ -1424,17 +1491,14 @@ __device__ __forceinline__ void reorder_scatter_atom(const MDArgs& a, const Cell
   a.vx[q] = r.vx[q]; a.vy[q] = r.vy[q]; a.vz[q] = r.vz[q];
   const typename P::S sq = r.s[q];
   P::store_xyz(a.s_cur, q, sq);
-  P::store_xyz(a.sb, q, sq);
+  a.sb[q] = P::quant(sq);
   a.abin[q] = r.abin[q];
   const int g = r.gid[q];
   a.gid[q] = g;
   const int4 b0 = a.bond0[C.off + g];
-  int4 b;
-  b.x = b0.x < 0 ? -1 : a.pos_of[C.off + b0.x];
-  b.y = b0.y < 0 ? -1 : a.pos_of[C.off + b0.y];
-  b.z = b0.z < 0 ? -1 : a.pos_of[C.off + b0.z];
-  b.w = b0.w < 0 ? -1 : a.pos_of[C.off + b0.w];
-  a.bond[q] = b;
+  const int self = (int)(q - C.off);
+  store_bonds(a, q, b0.x < 0 ? self : a.pos_of[C.off + b0.x], b0.y < 0 ? self : a.pos_of[C.off + b0.y],
+              b0.z < 0 ? self : a.pos_of[C.off + b0.z], b0.w < 0 ? self : a.pos_of[C.off + b0.w]);
 }
 
 template <class P>
@@ -1508,7 +1572,8 @@ __global__ __launch_bounds__(TILE) void k_reset_order(MDArgs a, int first, int c
   const int li = (int)(i - a.cells[t.cell].off);
   a.gid[i] = li;
   a.pos_of[i] = li;
-  a.bond[i] = a.bond0[i];
+  const int4 b0 = a.bond0[i];
+  store_bonds(a, i, b0.x < 0 ? li : b0.x, b0.y < 0 ? li : b0.y, b0.z < 0 ? li : b0.z, b0.w < 0 ? li : b0.w);
 }
 
 // Verlet list of every atom (after the reorder, so positions are in bin order): cell-local j with
@@ -1748,6 +1813,12 @@ __device__ inline void set_box_fields(CellDev& C, double rcs) {
     C.Hm[q] = hs;
     C.Hd[q] = hs * TWOM32;
   }
+  // the 16-bit build reference is within 2^-17 of the position in each scaled coordinate, so a
+  // measured displacement is within |H|_F sqrt(3) 2^-17 of the true one (with a relative margin for
+  // the FP32 arithmetic of the check)
+  double hf = 0.0;
+  for (int q = 0; q < 6; ++q) hf += C.H[up[q]] * C.H[up[q]];
+  C.qeps = (float)(1.001 * sqrt(3.0 * hf) * 0x1.0p-17);
   double w[3];
   box_widths(C.H, w);
   for (int q = 0; q < 3; ++q) C.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / rcs)));
@@ -1791,6 +1862,7 @@ __global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double 
     C.H[k] = S.Hn[k]; C.Q[k] = S.Q[k]; C.R[k] = S.R[k]; C.Rprev[k] = S.R[k]; C.F[k] = S.F[k];
   }
   C.J = S.J;
+  const float qeps_old = C.qeps;
   set_box_fields(C, rcs);
   for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
   C.wcount = 0;
@@ -1801,11 +1873,13 @@ __global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double 
     e2 += d * d;
   }
   const double grow = 1.0 + sqrt(e2);
-  const bool moved = (double)C.dmax2 * grow * grow >= (double)hs2;
-  if (force_build || C.rebuild || !(hs2 > 0.0f) || moved) {
+  const double u = (sqrt((double)C.dmax2) + (double)qeps_old) * grow;   // bound on the true displacement
+  const float hs2m = hs2 > 0.0f ? measured_threshold((double)hs2, C.qeps) : -1.0f;
+  const bool moved = !(hs2 > 0.0f) || u * u >= (double)hs2;
+  if (force_build || C.rebuild || moved || !(hs2m > 0.0f)) {
     C.rebuild = 1;
   } else {
-    C.hs2 = hs2;
+    C.hs2 = hs2m;
   }
   C.pending = 1;
 }

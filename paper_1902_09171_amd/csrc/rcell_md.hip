@@ -44,8 +44,10 @@ struct rcell_ctx {
   // device memory
   double *x = nullptr, *y = nullptr, *z = nullptr, *vx = nullptr, *vy = nullptr, *vz = nullptr;
   void *fx = nullptr, *fy = nullptr, *fz = nullptr;
-  void *s[2] = {nullptr, nullptr}, *sb = nullptr;
-  int4 *bond = nullptr, *bond0 = nullptr;
+  void *s[2] = {nullptr, nullptr};
+  uint2* sb = nullptr;            // build reference, 16 bits per scaled coordinate
+  void* bond = nullptr;           // 4 partner slots per atom, 16-bit when list16 else 32-bit
+  int4* bond0 = nullptr;
   int *gid = nullptr, *pos_of = nullptr;
   char* pscr = nullptr;           // reorder scratch rows
   void* nbr = nullptr;
@@ -178,7 +180,8 @@ MDArgs make_args(const rcell_ctx* c) {
   a.x = c->x; a.y = c->y; a.z = c->z; a.vx = c->vx; a.vy = c->vy; a.vz = c->vz;
   a.fx = c->fx; a.fy = c->fy; a.fz = c->fz;
   a.s_cur = c->s[c->cur]; a.s_nxt = c->s[1 - c->cur]; a.sb = c->sb;
-  a.bond = c->bond; a.bond0 = c->bond0; a.gid = c->gid; a.pos_of = c->pos_of; a.pscr = c->pscr;
+  a.bond = c->bond; a.bond0 = c->bond0; a.bond16 = c->list16 ? 1 : 0;
+  a.gid = c->gid; a.pos_of = c->pos_of; a.pscr = c->pscr;
   a.nn = c->nn; a.nbr = c->nbr; a.npad = c->npad; a.maxnb = c->maxnb;
   a.cells = c->cells; a.tiles = c->tiles; a.parts = c->parts; a.ntiles = c->ntiles; a.ncells = c->ncells;
   a.abin = c->abin; a.bcount = c->bcount; a.bstart = c->bstart; a.bnum = c->bnum; a.bfill = c->bfill;
@@ -592,11 +595,12 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
   const size_t fsz = sizeof(double);
   const size_t ssz = c->fp64 ? sizeof(S64) : sizeof(int4);
   int e;
-  char *f0, *s0, *s1, *sbp;
+  char *f0, *s0, *s1, *bondp;
   if ((e = dalloc(c, &c->x, N)) || (e = dalloc(c, &c->y, N)) || (e = dalloc(c, &c->z, N)) ||
       (e = dalloc(c, &c->vx, N)) || (e = dalloc(c, &c->vy, N)) || (e = dalloc(c, &c->vz, N)) ||
       (e = dalloc(c, &f0, 3 * fsz * N)) || (e = dalloc(c, &s0, ssz * N)) || (e = dalloc(c, &s1, ssz * N)) ||
-      (e = dalloc(c, &sbp, ssz * N)) || (e = dalloc(c, &c->bond, N)) || (e = dalloc(c, &c->bond0, N)) ||
+      (e = dalloc(c, &c->sb, N)) || (e = dalloc(c, &bondp, (c->list16 ? 8 : 16) * (size_t)N)) ||
+      (e = dalloc(c, &c->bond0, N)) ||
       (e = dalloc(c, &c->gid, N)) || (e = dalloc(c, &c->pos_of, N)) ||
       (e = dalloc(c, &c->pscr, (6 * sizeof(double) + ssz + 2 * sizeof(int)) * (size_t)c->npad)) ||
       (e = dalloc(c, &c->nn, N)) ||
@@ -608,7 +612,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
       (e = dalloc(c, &c->work_kstart, ncells + 1)) || (e = dalloc(c, &c->work_count, 4)))
     return bail(e);
   c->fx = f0; c->fy = f0 + fsz * N; c->fz = f0 + 2 * fsz * N;
-  c->s[0] = s0; c->s[1] = s1; c->sb = sbp;
+  c->s[0] = s0; c->s[1] = s1; c->bond = bondp;
   if ((e = ensure_list_capacity(c, list_capacity(dens, rcs)))) return bail(e);
 
   // ---- marshal the initial state (AoS -> SoA), bonds -> per-atom partner slots
