@@ -170,11 +170,12 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def gpu_sample_error(rcell, params, cells, F, nsteps, s_ora, lanes):
+def gpu_sample_error(rcell, params, cells, F, nsteps, s_ora, lanes, bin_factor=1):
     """The same sample on the GPU from the same initial state: max relative stress deviation."""
     import numpy as np
     g = rcell.RCellBatch(params, cells)
     g.set_lanes(lanes)
+    g.set_bin_factor(bin_factor)
     g.set_deformation(F)
     g.get_stress()
     g.run(nsteps)
@@ -193,6 +194,15 @@ def kernel_avg(g, slot, run_again):
     ms1, n1 = g.prof_read(1 - slot)
     g.prof_enable(False)
     return (ms / 1e3 / max(n, 1), n), (ms1 / 1e3 / max(n1, 1), n1)
+
+
+def tune(g, args):
+    """The batch engine's knobs: rcell_autotune (bin factor, then lanes per atom) unless --lanes
+    fixes the lanes; returns (lanes, bin_factor)."""
+    if args.lanes == 0:
+        return g.autotune(use_cache=True)
+    g.set_lanes(args.lanes)
+    return g.lanes(), g.bin_factor()
 
 
 def md_line(args, workload, value, elapsed, natoms, config, roofline, extra=None, dtype=None):
@@ -228,7 +238,7 @@ def bench_cu_element(args, torch, rcell, configs, ncells=8):
     sig_dev = torch.zeros((ncells, 6), dtype=torch.float64, device=dev)
     P_dev = torch.zeros((ncells, 9), dtype=torch.float64, device=dev)
     g.set_deformation_dev(F_dev[0].data_ptr())
-    lanes = g.set_lanes(args.lanes)
+    lanes, binf = tune(g, args)
 
     def load_step(k):
         g.set_deformation_dev(F_dev[k % nload].data_ptr())
@@ -261,7 +271,7 @@ def bench_cu_element(args, torch, rcell, configs, ncells=8):
                   {"description": what + ", Sutton-Chen EAM, 300 K, dt 1 fs, rotated uniaxial F ramp to 5 %, "
                                          "100 MD steps per load step",
                    "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
-                   "lanes_per_atom": lanes}, roofline)
+                   "lanes_per_atom": lanes, "bin_factor": binf}, roofline)
     if not args.no_cpu_baseline:
         sub = list(range(min(ncells, max(8, host_threads()))))
         cells8, F8 = [cfg["cells"][c] for c in sub], cfg["F_path"][0][sub]
@@ -269,7 +279,7 @@ def bench_cu_element(args, torch, rcell, configs, ncells=8):
                                   f"first load step of the first {len(sub)} cells")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cells8, F8,
-                                                           args.cpu_sample_steps, s_ora, lanes)
+                                                           args.cpu_sample_steps, s_ora, lanes, binf)
     return out
 
 
@@ -287,7 +297,7 @@ def bench_kg_single(args, torch, rcell, configs):
     F_dev = torch.tensor(np.ascontiguousarray(cfg["F_path"]), dtype=torch.float64, device=dev)
     sig_dev = torch.zeros((1, 6), dtype=torch.float64, device=dev)
     nF = len(cfg["F_path"])
-    lanes = g.set_lanes(args.lanes)
+    lanes, binf = tune(g, args)
 
     def md_step(k):                                   # F of step k, one MD step, stress every 100
         g.set_deformation_dev(F_dev[k % nF].data_ptr())
@@ -319,7 +329,7 @@ def bench_kg_single(args, torch, rcell, configs):
                   {"description": "one Kremer-Grest cell, 20 chains x 50 beads, FP64, F ramped to a 20 % "
                                   "uniaxial isochoric stretch over 1000 MD steps (new F before every step), "
                                   "stress every 100 steps", "cells": 1, "atoms": natoms,
-                   "md_steps_per_step": 1, "lanes_per_atom": lanes}, roofline,
+                   "md_steps_per_step": 1, "lanes_per_atom": lanes, "bin_factor": binf}, roofline,
                   extra={"us_per_md_step_with_new_F": elapsed / args.steps * 1e6,
                          "us_per_md_step_plain_run": plain_us}, dtype="f64")
     if not args.no_cpu_baseline:
@@ -327,7 +337,7 @@ def bench_kg_single(args, torch, rcell, configs):
                                   "the cell at the first F of the ramp")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, cfg["params"], cfg["cells"], cfg["F_path"][0],
-                                                           1000, s_ora, lanes)
+                                                           1000, s_ora, lanes, binf)
     return out
 
 
@@ -377,14 +387,15 @@ def bench_kg_batched(args, torch, rcell, configs, glassy=False):
     res = make_cells(_kg_glassy_cell if glassy else _kg_batched_cell, list(range(ncells)))
     cells = [r[0] for r in res]
     F = np.stack([r[1] for r in res])
-    params = configs.kg_glassy_params(precision="mixed") if glassy else configs.kg_params(precision="mixed")
+    params = (configs.kg_glassy_params(precision="mixed") if glassy else
+              configs.kg_params(precision="mixed", skin=0.55))      # the fastest skin of a sweep
     natoms = sum(len(c["x"]) for c in cells)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     log(f"creating the batch: {natoms} beads")
     g = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)
     g.set_deformation(F)
-    lanes = g.set_lanes(args.lanes)
+    lanes, binf = tune(g, args)
     sig_dev = torch.zeros((ncells, 6), dtype=torch.float64, device=dev)
 
     def step():
@@ -417,14 +428,14 @@ def bench_kg_batched(args, torch, rcell, configs, glassy=False):
     out = md_line(args, name, natoms * MD_PER_STEP * args.steps / elapsed, elapsed, natoms,
                   {"description": what + "; 100 MD steps per step",
                    "cells": ncells, "atoms": natoms, "md_steps_per_step": MD_PER_STEP,
-                   "lanes_per_atom": lanes, "rebuilds": g.rebuilds()}, roofline)
+                   "lanes_per_atom": lanes, "bin_factor": binf, "skin": params["skin"], "rebuilds": g.rebuilds()}, roofline)
     if not args.no_cpu_baseline:
         sub = list(range(min(ncells, max(16, host_threads()))))
         cb, s_ora = oracle_sample(params, [cells[c] for c in sub], F[sub], 20,
                                   f"the first {len(sub)} cells of the batch")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F[sub], 20,
-                                                           s_ora, lanes)
+                                                           s_ora, lanes, binf)
     return out
 
 
@@ -449,8 +460,9 @@ def bench_glassy_rates(args, torch, rcell, configs):
     stream = torch.cuda.current_stream(dev)
     A = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)      # continuous
     B = rcell.RCellBatch(params, cells, stream=stream.cuda_stream)      # load steps
-    lanes = A.set_lanes(args.lanes)
+    lanes, binf = tune(A, args)
     B.set_lanes(lanes)
+    B.set_bin_factor(binf)
     nst = args.steps                  # timed MD steps of the direct path, each with its own F
     nld = max(1, nst // N)            # load steps of N MD steps on the r-cell path
     F_cont = np.stack([np.stack([uniaxial_isochoric(r * dt * (t + 1)) for r in RATES]) for t in range(nst)])
@@ -501,7 +513,7 @@ def bench_glassy_rates(args, torch, rcell, configs):
                   {"description": "direct MD at constant engineering strain rates 0.01, 0.015, 0.02 / tau (new "
                                   "isochoric uniaxial F before every MD step), one glassy Kremer-Grest cell of "
                                   "100 x 100 beads per rate (LJ to 2.5 sigma, T = 0.1, dt 0.005)",
-                   "cells": len(RATES), "atoms": natoms, "md_steps_per_step": 1, "lanes_per_atom": lanes},
+                   "cells": len(RATES), "atoms": natoms, "md_steps_per_step": 1, "lanes_per_atom": lanes, "bin_factor": binf},
                   roofline,
                   extra={"load_step_path_atom_steps_per_s": natoms * nld * N / elapsed_b,
                          "tensile_stress_curves": {"columns": ["strain", "direct MD (mean over the load step's "
@@ -514,15 +526,19 @@ def bench_glassy_rates(args, torch, rcell, configs):
     return out
 
 
-# The FE workloads: mesh, r-cell generator, MD steps per load step and the text of the line.
+# The FE workloads: mesh, r-cell generator, MD steps per load step, neighbour skin and the text of
+# the line.  The skin changes speed only (never the pairs within rc); the values are the fastest of a
+# sweep on one MI355X (0.3 - 0.8 sigma): the bar's 40 000-bead cells rebuild more often than smaller
+# ones (the largest displacement is taken over more atoms), so a wider skin pays there.
 FE_WORKLOADS = {
-    "fe_bar": dict(mesh=("hex8", (8, 2, 2), (200.0, 50.0, 50.0), 0.95), cell=_fe_bar_cell, md=500,
+    "fe_bar": dict(mesh=("hex8", (8, 2, 2), (200.0, 50.0, 50.0), 0.95), cell=_fe_bar_cell, md=500, skin=0.7,
                    text="explicit hex8 bar 8x2x2 elements x 8 Gauss points = 256 Kremer-Grest r-cells of 400 "
                         "chains x 100 beads, imperfection-seeded neck"),
-    "fe_tet": dict(mesh=("tet4", (5, 2, 2), (150.0, 150.0, 150.0), 1.0), cell=_fe_tet_cell, md=500,
+    "fe_tet": dict(mesh=("tet4", (5, 2, 2), (150.0, 150.0, 150.0), 1.0), cell=_fe_tet_cell, md=500, skin=0.55,
                    text="the paper's cubic polymer specimen: 100 C3D4 tetrahedra, one quadrature point each = 100 "
                         "Kremer-Grest r-cells of 100 chains x 100 beads (10^6 beads)"),
     "fe_scaling": dict(mesh=("tet4", (8, 5, 5), (200.0, 200.0, 200.0), 1.0), cell=_fe_scaling_cell, md=100,
+                       skin=0.55,
                        text="the paper's scaling system on one GPU: 1000 C3D4 tetrahedra = 1000 Kremer-Grest "
                             "r-cells of 100 chains x 100 beads (10^7 beads)"),
 }
@@ -537,11 +553,11 @@ def bench_fe(args, torch, rcell, configs, name):
     mesh = (fe.Hex8Bar if kind == "hex8" else fe.Tet4Bar)(nel=nel, size=size, rho0=0.85, imperfection=imp)
     log(f"generating {mesh.ngp} r-cells")
     cells = make_cells(spec["cell"], list(range(mesh.ngp)))
-    params = configs.kg_params(precision="mixed")
+    params = configs.kg_params(precision="mixed", skin=spec["skin"])
     natoms = sum(len(c["x"]) for c in cells)
     log(f"creating the batch: {natoms} beads")
     md = fe.MDStress(params, cells, MD_PER_LOAD)
-    lanes = md.g.set_lanes(args.lanes)
+    lanes, binf = tune(md.g, args)
     dt = MD_PER_LOAD * params["dt"]
     # 1 % nominal strain per load step
     bar = fe.ExplicitBar(mesh, md, dt=dt, pull_velocity=0.01 * mesh.size[0] / dt, damping=0.2)
@@ -565,7 +581,7 @@ def bench_fe(args, torch, rcell, configs, name):
                   {"description": spec["text"] + f", 1 % nominal strain per load step, {MD_PER_LOAD} MD steps "
                                                  "per load step",
                    "cells": mesh.ngp, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
-                   "lanes_per_atom": lanes, "rebuilds": md.g.rebuilds()}, roofline,
+                   "lanes_per_atom": lanes, "bin_factor": binf, "skin": params["skin"], "rebuilds": md.g.rebuilds()}, roofline,
                   extra={"fe_wall_s_per_load_step": elapsed / args.steps})
     if not args.no_cpu_baseline:
         sub = list(range(min(len(cells), host_threads())))
@@ -574,7 +590,7 @@ def bench_fe(args, torch, rcell, configs, name):
                                   f"{len(sub)} of the r-cells (one per host thread), from rest")
         out["cpu_baseline"] = cb
         out["stress_rel_err_vs_oracle"] = gpu_sample_error(rcell, params, [cells[c] for c in sub], F, 20,
-                                                           s_ora, lanes)
+                                                           s_ora, lanes, binf)
     return out
 
 

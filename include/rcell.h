@@ -167,6 +167,22 @@ int rcell_set_lanes(rcell_ctx* ctx, int32_t lanes);
  * reduction of each MD step in the same launch, which makes a step six launches shorter. */
 int rcell_set_build_mode(rcell_ctx* ctx, int32_t mode);
 int rcell_get_lanes(rcell_ctx* ctx, int32_t* lanes);
+/* Width of the neighbour-build bins: at least (rc + skin) / f along every perpendicular box width,
+ * with a stencil of +- f bins (f = 1, the default, or 2; else RCELL_ERR_ARG).  Narrower bins give
+ * fewer candidates per atom for wider skins, more bins to scan.  Takes effect at each cell's next
+ * neighbour build; the list in place stays valid.  The pair set within rc never depends on it. */
+int rcell_set_bin_factor(rcell_ctx* ctx, int32_t f);
+int rcell_get_bin_factor(rcell_ctx* ctx, int32_t* f);
+/* Autotune of the batch engine: the bin factor, by rebuilding every cell at its current positions
+ * with each factor (best of three timed rounds), and then the lanes per atom as rcell_set_lanes(0)
+ * does.  The per-atom state, the list and the cell table are copied aside before the trials and
+ * copied back after them (a temporary device buffer of ~100 bytes per atom plus the list,
+ * RCELL_ERR_OOM if it cannot be allocated), so the state and the trajectory that follows are those
+ * of rcell_set_lanes / rcell_set_bin_factor called with the chosen values.  use_cache != 0 reuses
+ * the choice of an earlier call in this process with the same potential, precision, list width,
+ * skin, densest cell and cell / batch size ranges instead of timing again.  lanes and bin_factor
+ * (either may be NULL) receive the choice. */
+int rcell_autotune(rcell_ctx* ctx, int32_t use_cache, int32_t* lanes, int32_t* bin_factor);
 /* MD steps inside a run are replayed from captured HIP graphs of `steps` steps (even; default
  * 10); 0 launches every kernel individually.  Results are identical either way. */
 int rcell_set_graph_steps(rcell_ctx* ctx, int32_t steps);

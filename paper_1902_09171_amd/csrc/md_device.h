@@ -129,6 +129,7 @@ struct MDArgs {
   // order, and the exclusive prefix sums of their tiles and of their 64-bin chunks (ncell + 1
   // entries each); work_count[0..2] = cells, tiles, chunks
   int *work_cells, *work_tstart, *work_kstart, *work_count;
+  int bin_factor;                  // bins at least (rc + skin) / bin_factor wide; stencil +- bin_factor
   // integrator constants (computed once on the host, documented expressions)
   double dt, h, drag, c24, mmv, half_skin2, rcs2;
   double fire_ftol2;               // statics: converged when max_i |f_i|^2 <= fire_ftol2
@@ -1588,7 +1589,9 @@ __global__ __launch_bounds__(TILE) void k_reset_order(MDArgs a, int first, int c
 // TILE / BUILD_ATOMS blocks cover one tile.
 constexpr int LPA = 8;
 constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
-constexpr int MAX_RANGES = 18;   // 3 x 3 columns, each at most two ranges
+constexpr int MAX_BIN_FACTOR = 2;
+constexpr int STENCIL = 2 * MAX_BIN_FACTOR + 1;
+constexpr int MAX_RANGES = STENCIL * STENCIL * 2;   // columns of the stencil, each at most two ranges
 template <class P, class LT>
 __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int part, int2 (*rng)[MAX_RANGES]) {
   const CellDev& C = a.cells[t.cell];
@@ -1599,32 +1602,36 @@ __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int p
   const typename P::S si = P::load(a.s_cur, i);
   const int pk = a.abin[i];
   const int bb[3] = {pk & BIN_MASK, (pk >> BIN_BITS) & BIN_MASK, pk >> (2 * BIN_BITS)};
-  // neighbour bin coordinates per dimension: b - 1, b, b + 1 (periodic), or every bin when the
-  // dimension has fewer than three
-  int lst[3][3], cnt[3];
+  // Neighbour bin coordinates per dimension: b - f ... b + f (periodic) for bins at least
+  // (rc + skin) / f wide (a pair within rc + skin is at most f bins apart in every dimension), or
+  // every bin when the dimension has fewer than 2 f + 1
+  const int fb = a.bin_factor;
+  int lst[3][STENCIL], cnt[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int nbq = C.nb[q];
-    if (nbq >= 3) {
-      cnt[q] = 3;
-      lst[q][0] = bb[q] == 0 ? nbq - 1 : bb[q] - 1;
-      lst[q][1] = bb[q];
-      lst[q][2] = bb[q] + 1 == nbq ? 0 : bb[q] + 1;
+    if (nbq >= 2 * fb + 1) {
+      cnt[q] = 2 * fb + 1;
+      for (int k = 0; k <= 2 * fb; ++k) {
+        const int v = bb[q] - fb + k;
+        lst[q][k] = v < 0 ? v + nbq : (v >= nbq ? v - nbq : v);
+      }
     } else {
       cnt[q] = nbq;
-      lst[q][0] = 0; lst[q][1] = 1; lst[q][2] = 2;
+      for (int k = 0; k < STENCIL; ++k) lst[q][k] = k;
     }
   }
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
   const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
-  // z part of every column: bins [z0, z1], or [z0, z1] and [z2, z2] at the periodic edge
+  // z part of every column: bins [z0, z1], or two such ranges across the periodic edge
   const int nbz = C.nb[2];
   int zr[2][2] = {{0, nbz - 1}, {0, 0}}, nzr = 1;
-  if (nbz >= 3) {
-    if (bb[2] == 0) { zr[0][0] = 0; zr[0][1] = 1; zr[1][0] = zr[1][1] = nbz - 1; nzr = 2; }
-    else if (bb[2] == nbz - 1) { zr[0][0] = nbz - 2; zr[0][1] = nbz - 1; zr[1][0] = zr[1][1] = 0; nzr = 2; }
-    else { zr[0][0] = bb[2] - 1; zr[0][1] = bb[2] + 1; }
+  if (nbz >= 2 * fb + 1) {
+    const int lo = bb[2] - fb, hi = bb[2] + fb;
+    if (lo < 0) { zr[0][0] = 0; zr[0][1] = hi; zr[1][0] = lo + nbz; zr[1][1] = nbz - 1; nzr = 2; }
+    else if (hi >= nbz) { zr[0][0] = lo; zr[0][1] = nbz - 1; zr[1][0] = 0; zr[1][1] = hi - nbz; nzr = 2; }
+    else { zr[0][0] = lo; zr[0][1] = hi; }
   }
   const int nrange = cnt[0] * cnt[1] * nzr;
   int2* rg = rng[threadIdx.x / LPA];
@@ -1777,8 +1784,8 @@ __device__ inline void tilt_reduce(double H[9]) {
   if (fabs(H[1]) > 0.5 * H[0]) { const double k = floor(H[1] / H[0] + 0.5); H[1] -= k * H[0]; }
 }
 
-// stage everything a deformation needs; no state is modified
-__global__ void k_qr_stage(const double* Fall, const CellDev* cells, Stage* st, int ncells, double rcs) {
+// stage everything a deformation needs; no state is modified (bw: the bin width, (rc + skin) / f)
+__global__ void k_qr_stage(const double* Fall, const CellDev* cells, Stage* st, int ncells, double rcs, double bw) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   Stage& S = st[c];
@@ -1798,13 +1805,13 @@ __global__ void k_qr_stage(const double* Fall, const CellDev* cells, Stage* st, 
   box_widths(S.Hn, w);
   S.wmin = fmin(w[0], fmin(w[1], w[2]));
   if (rcs > 0.5 * S.wmin) { S.status = ST_BOX; return; }
-  for (int q = 0; q < 3; ++q) S.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / rcs)));
+  for (int q = 0; q < 3; ++q) S.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / bw)));
   S.nbins = S.nb[0] * S.nb[1] * S.nb[2];
   S.density = (double)C.n / fabs(det3(S.Hn));
 }
 
-// fill the derived box fields of a cell from C.H
-__device__ inline void set_box_fields(CellDev& C, double rcs) {
+// fill the derived box fields of a cell from C.H (bw: the bin width)
+__device__ inline void set_box_fields(CellDev& C, double bw) {
   upper_inv(C.H, C.Hi);
   C.V = det3(C.H);
   const int up[6] = {0, 1, 2, 4, 5, 8};
@@ -1821,8 +1828,8 @@ __device__ inline void set_box_fields(CellDev& C, double rcs) {
   C.qeps = (float)(1.001 * sqrt(3.0 * hf) * 0x1.0p-17);
   double w[3];
   box_widths(C.H, w);
-  for (int q = 0; q < 3; ++q) C.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / rcs)));
-  // never exceed the bins allocated to this cell: coarser bins are still valid (>= rc + skin)
+  for (int q = 0; q < 3; ++q) C.nb[q] = min(BIN_MASK, max(1, (int)floor(w[q] / bw)));
+  // never exceed the bins allocated to this cell: coarser bins are still valid (>= the bin width)
   while (C.nb[0] * C.nb[1] * C.nb[2] > max(C.bin_cap, 1)) {
     int q = 0;
     if (C.nb[1] > C.nb[q]) q = 1;
@@ -1853,7 +1860,8 @@ __device__ inline float kept_list_threshold(const CellDev& C, double rc, double 
   return hs > 0.0 ? (float)(hs * hs) : -1.0f;
 }
 
-__global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double rc, double rcs, int force_build) {
+__global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double rc, double rcs, double bw,
+                            int force_build) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
   CellDev& C = cells[c];
@@ -1863,7 +1871,7 @@ __global__ void k_qr_commit(CellDev* cells, const Stage* st, int ncells, double 
   }
   C.J = S.J;
   const float qeps_old = C.qeps;
-  set_box_fields(C, rcs);
+  set_box_fields(C, bw);
   for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
   C.wcount = 0;
   const float hs2 = kept_list_threshold(C, rc, rcs);
@@ -1902,11 +1910,11 @@ __global__ __launch_bounds__(TILE) void k_remap(MDArgs a, const Stage* st) {
 }
 
 // set a cell's box from H (create / set_state) and request a rebuild + prime
-__global__ void k_set_box(CellDev* cells, int first, int count, double rcs) {
+__global__ void k_set_box(CellDev* cells, int first, int count, double bw) {
   const int c = first + blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= first + count) return;
   CellDev& C = cells[c];
-  set_box_fields(C, rcs);
+  set_box_fields(C, bw);
   for (int q = 0; q < 6; ++q) C.wsum[q] = 0.0;
   C.wcount = 0;
   C.rebuild = 1;
@@ -2006,6 +2014,13 @@ __global__ void k_return_batch(const double* F, const double* smd, int n, double
     const double J = R[0] * R[4] * R[8];
     for (int q = 0; q < 9; ++q) P[9 * c + q] = J * Pm[q];
   }
+}
+
+// a new bin width for every cell: bin counts recomputed from the box; the list stays valid and the
+// next build uses the new bins
+__global__ void k_set_bin_width(CellDev* cells, int ncells, double bw) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncells) set_box_fields(cells[c], bw);
 }
 
 __global__ void k_set_pending(CellDev* cells, int first, int count) {

@@ -9,7 +9,10 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/rcell.h"
@@ -31,6 +34,7 @@ struct rcell_ctx {
   int ntiles = 0;
   int maxnb = 0;
   int lanes = 1;
+  int bin_factor = 1;             // bins at least (rc + skin) / bin_factor wide
   int cur = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -38,6 +42,7 @@ struct rcell_ctx {
   std::vector<int> off, n, tile_off, ntile, bin_off, bin_cap;
   long long bins_total = 0, bins_alloc = 0;
   std::vector<double> occ;        // expected atoms per bin of each cell
+  double density_max = 0.0;       // the densest cell at create (atoms per volume)
   double fire_ftol2 = 0.0;        // statics: convergence threshold and move limit of the current call
   int fire_max_iter = 0;
   int sort_cap = 256;             // keys staged in LDS per wave by the bin sort
@@ -170,6 +175,8 @@ int bins_for(const double H[9], double rcs) {
   return std::max(1, (int)std::floor(V / (rcs * rcs * rcs)));
 }
 
+double bin_width(const rcell_ctx* c) { return (c->p.rc + c->p.skin) / c->bin_factor; }
+
 int list_capacity(double density, double rcs) {
   const double expect = density * 4.0 / 3.0 * M_PI * rcs * rcs * rcs;
   return (int)std::ceil(1.6 * expect + 24.0);
@@ -190,6 +197,7 @@ MDArgs make_args(const rcell_ctx* c) {
   a.bins_total = c->bins_total;
   a.work_cells = c->work_cells; a.work_tstart = c->work_tstart; a.work_kstart = c->work_kstart;
   a.work_count = c->work_count;
+  a.bin_factor = c->bin_factor;
   const rcell_params& p = c->p;
   // integrator constants: the same expressions, in the same order, as the method's definition
   a.dt = p.dt;
@@ -412,6 +420,16 @@ int first_error(rcell_ctx* c, const std::vector<int>& st) {
   return RCELL_OK;
 }
 
+// the host's bin layout (offsets, capacities) into the device cell table
+int push_bin_layout(rcell_ctx* c) {
+  int *doff = c->iscratch, *dcap = c->iscratch + c->ncells;
+  HIPCHK(c, hipMemcpyAsync(doff, c->bin_off.data(), sizeof(int) * c->ncells, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dcap, c->bin_cap.data(), sizeof(int) * c->ncells, hipMemcpyHostToDevice, c->stream));
+  hipLaunchKernelGGL(k_set_bins, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->cells, c->ncells, doff, dcap);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RCELL_OK;
+}
+
 // lay out bins with capacity caps (>= need), update the device cell table
 int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
   drop_graphs(c);
@@ -442,12 +460,7 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
   HIPCHK(c, hipMemcpyAsync(c->bin_cell, owner.data(), sizeof(int) * total, hipMemcpyHostToDevice, c->stream));
   c->bin_off = off;
   c->bin_cap = cap;
-  int *doff = c->iscratch, *dcap = c->iscratch + c->ncells;
-  HIPCHK(c, hipMemcpyAsync(doff, off.data(), sizeof(int) * c->ncells, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(dcap, cap.data(), sizeof(int) * c->ncells, hipMemcpyHostToDevice, c->stream));
-  hipLaunchKernelGGL(k_set_bins, dim3((c->ncells + 127) / 128), dim3(128), 0, c->stream, c->cells, c->ncells, doff, dcap);
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return RCELL_OK;
+  return push_bin_layout(c);
 }
 
 int ensure_list_capacity(rcell_ctx* c, int need) {
@@ -483,7 +496,8 @@ void destroy_all(rcell_ctx* c) {
 int deformation_common(rcell_ctx* c, const double* F_dev) {
   const int nc = c->ncells;
   const double rcs = c->p.rc + c->p.skin;
-  hipLaunchKernelGGL(k_qr_stage, dim3((nc + 63) / 64), dim3(64), 0, c->stream, F_dev, c->cells, c->stage, nc, rcs);
+  hipLaunchKernelGGL(k_qr_stage, dim3((nc + 63) / 64), dim3(64), 0, c->stream, F_dev, c->cells, c->stage, nc, rcs,
+                     bin_width(c));
   std::vector<Stage> st(nc);
   HIPCHK(c, hipMemcpyAsync(st.data(), c->stage, sizeof(Stage) * nc, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -507,11 +521,49 @@ int deformation_common(rcell_ctx* c, const double* F_dev) {
   const int relist = cap > c->maxnb;               // a reallocated list must be rebuilt everywhere
   if ((e = ensure_list_capacity(c, cap))) return e;
   hipLaunchKernelGGL(k_qr_commit, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, c->stage, nc, c->p.rc,
-                     rcs, relist);
+                     rcs, bin_width(c), relist);
   const MDArgs a = make_args(c);
   if (c->fp64) hipLaunchKernelGGL(k_remap<FP64>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a, c->stage);
   else hipLaunchKernelGGL(k_remap<Mixed>, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, a, c->stage);
   return prime(c);
+}
+
+// Bins of every cell at the width (rc + skin) / f for its current box: the layout grows when a
+// cell needs more bins; the list stays valid and the next build uses the new bins.
+int apply_bin_factor(rcell_ctx* c, int f) {
+  const int nc = c->ncells;
+  std::vector<CellDev> hc(nc);
+  HIPCHK(c, hipMemcpyAsync(hc.data(), c->cells, sizeof(CellDev) * nc, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double bw = (c->p.rc + c->p.skin) / f;
+  std::vector<int> need(nc);
+  bool grow = false;
+  for (int k = 0; k < nc; ++k) {
+    need[k] = bins_for(hc[k].H, bw);
+    set_occupancy(c, k, (double)c->n[k] / bins_exact(hc[k].H, bw));
+    grow = grow || need[k] > c->bin_cap[k];
+  }
+  drop_graphs(c);                                  // the captured steps carry the bin factor
+  c->bin_factor = f;
+  int e;
+  if (grow && (e = layout_bins(c, need))) return e;
+  hipLaunchKernelGGL(k_set_bin_width, dim3((nc + 63) / 64), dim3(64), 0, c->stream, c->cells, nc, bw);
+  HIPCHK(c, hipGetLastError());
+  return RCELL_OK;
+}
+
+// choices of rcell_autotune, per process, keyed by what decides them: potential, precision, list
+// entry width, skin, the densest cell and the size ranges of the cells and of the batch
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, long, long, int, int>, std::pair<int, int>> g_tune_cache;
+
+std::tuple<int, int, int, long, long, int, int> tune_key(const rcell_ctx* c) {
+  double dens = 0.0;
+  for (int k = 0; k < c->ncells; ++k) dens = std::max(dens, (double)c->n[k]);
+  const int nmax = (int)std::floor(std::log2(std::max(1.0, dens)));
+  return std::make_tuple(c->p.potential, c->p.precision, c->list16 ? 1 : 0, std::lround(c->p.skin * 1000.0),
+                         std::lround(c->density_max * 100.0), nmax,
+                         (int)std::floor(std::log2(std::max(1.0, (double)c->N))));
 }
 
 }  // namespace
@@ -571,18 +623,20 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
     c->ntile.push_back(nt);
     ntiles += nt;
     N += ci.natoms;
-    need_bins[k] = bins_for(H, rcs);
+    need_bins[k] = bins_for(H, rcs / c->bin_factor);
     dens = std::max(dens, ci.natoms / (H[0] * H[4] * H[8]));
   }
   if (N > (1ll << 31) - 1) return bail(fail(c, RCELL_ERR_ARG, "too many atoms"));
   c->N = N;
+  c->density_max = dens;
   c->npad = (N + 63) / 64 * 64;
   c->list16 = !c->fp64 && *std::max_element(c->n.begin(), c->n.end()) <= 65536;
   c->small_cells = *std::max_element(c->n.begin(), c->n.end()) <= PREP_ATOMS;
   c->cell_prep = c->small_cells;
   c->ntiles = ntiles;
   c->occ.assign(ncells, 0.0);
-  for (int k = 0; k < ncells; ++k) set_occupancy(c, k, (double)cells[k].natoms / bins_exact(cells[k].H0, rcs));
+  for (int k = 0; k < ncells; ++k)
+    set_occupancy(c, k, (double)cells[k].natoms / bins_exact(cells[k].H0, rcs / c->bin_factor));
 
   // ---- stream and memory
   if (hip_stream) {
@@ -669,7 +723,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
     return bail(fail(c, RCELL_ERR_DEVICE, "initial upload failed"));
   if ((e = layout_bins(c, need_bins))) return bail(e);
   hipLaunchKernelGGL(k_reset_order, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, make_args(c), 0, ncells);
-  hipLaunchKernelGGL(k_set_box, dim3((ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, ncells, rcs);
+  hipLaunchKernelGGL(k_set_box, dim3((ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, ncells, bin_width(c));
   if ((e = prime(c))) return bail(e);
   Gathered g;
   if ((e = gather(c, g))) return bail(e);
@@ -891,8 +945,8 @@ int rcell_set_state(rcell_ctx* c, int32_t cell, const double* x, const double* v
   if (0.5 * width_min(H) < rcs) return fail(c, RCELL_ERR_BOX, "box too small for rc + skin");
   const long long o = c->off[cell], n = c->n[cell];
   std::vector<int> need(c->bin_cap);
-  need[cell] = std::max(need[cell], bins_for(H, rcs));
-  set_occupancy(c, cell, (double)n / bins_exact(H, rcs));
+  need[cell] = std::max(need[cell], bins_for(H, bin_width(c)));
+  set_occupancy(c, cell, (double)n / bins_exact(H, bin_width(c)));
   int e;
   if (need[cell] > c->bin_cap[cell] && (e = layout_bins(c, need))) return e;
   if ((e = ensure_list_capacity(c, list_capacity(n / (H[0] * H[4] * H[8]), rcs)))) return e;
@@ -912,7 +966,7 @@ int rcell_set_state(rcell_ctx* c, int32_t cell, const double* x, const double* v
   HIPCHK(c, hipMemcpyAsync(c->cells + cell, &C, sizeof(CellDev), hipMemcpyHostToDevice, c->stream));
   // the state arrives in original order: identity order, then the rebuild reorders the cell
   hipLaunchKernelGGL(k_reset_order, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, make_args(c), cell, 1);
-  hipLaunchKernelGGL(k_set_box, dim3(1), dim3(64), 0, c->stream, c->cells, cell, 1, rcs);
+  hipLaunchKernelGGL(k_set_box, dim3(1), dim3(64), 0, c->stream, c->cells, cell, 1, bin_width(c));
   if ((e = prime(c))) return e;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return RCELL_OK;
@@ -1028,6 +1082,116 @@ int rcell_set_lanes(rcell_ctx* c, int32_t lanes) {
   for (int v = 1; v < NV; ++v)
     if (t[v] < t[best]) best = v;
   c->lanes = var[best];
+  return RCELL_OK;
+}
+
+int rcell_set_bin_factor(rcell_ctx* c, int32_t f) {
+  if (!c) return RCELL_ERR_ARG;
+  if (f < 1 || f > MAX_BIN_FACTOR) return fail(c, RCELL_ERR_ARG, "bin factor must be 1 or 2");
+  if (f == c->bin_factor) return RCELL_OK;
+  return apply_bin_factor(c, f);
+}
+
+int rcell_get_bin_factor(rcell_ctx* c, int32_t* f) {
+  if (!c || !f) return RCELL_ERR_ARG;
+  *f = c->bin_factor;
+  return RCELL_OK;
+}
+
+int rcell_autotune(rcell_ctx* c, int32_t use_cache, int32_t* lanes, int32_t* bin_factor) {
+  if (!c) return RCELL_ERR_ARG;
+  const auto key = tune_key(c);
+  int e;
+  if (use_cache) {
+    std::pair<int, int> hit{0, 0};
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) hit = it->second;
+    }
+    if (hit.first) {
+      if ((e = rcell_set_lanes(c, hit.first)) || (e = rcell_set_bin_factor(c, hit.second))) return e;
+      if (lanes) *lanes = c->lanes;
+      if (bin_factor) *bin_factor = c->bin_factor;
+      return RCELL_OK;
+    }
+  }
+  // The bin factor: every cell rebuilt at the current positions with each factor, best of three
+  // rounds taken in turn.  The build reorders atoms and rewrites the fixed-point coordinates, the
+  // build references, the partner slots, the list and the cell table, so those are copied aside
+  // first and copied back before every trial and at the end: the state is left exactly as found,
+  // with only the bins of the next build changed, as rcell_set_bin_factor leaves it.
+  const long long N = c->N;
+  const size_t ssz = c->fp64 ? sizeof(S64) : sizeof(int4);
+  const size_t lsz = (size_t)c->maxnb * (size_t)c->npad * (c->list16 ? sizeof(uint16_t) : sizeof(int));
+  struct Piece { void* dev; size_t bytes; };
+  const Piece pieces[] = {
+      {c->x, 8 * (size_t)N}, {c->y, 8 * (size_t)N}, {c->z, 8 * (size_t)N},
+      {c->vx, 8 * (size_t)N}, {c->vy, 8 * (size_t)N}, {c->vz, 8 * (size_t)N},
+      {c->s[c->cur], ssz * N}, {c->sb, sizeof(uint2) * N}, {c->gid, 4 * (size_t)N}, {c->pos_of, 4 * (size_t)N},
+      {c->bond, (c->list16 ? 8 : 16) * (size_t)N}, {c->nn, 4 * (size_t)N}, {c->nbr, lsz},
+      {c->cells, sizeof(CellDev) * (size_t)c->ncells}};
+  size_t total = 0;
+  for (const Piece& pc : pieces) total += (pc.bytes + 255) / 256 * 256;
+  char* keep = nullptr;
+  if (hipMalloc(&keep, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, RCELL_ERR_OOM, "autotune snapshot of " + std::to_string(total) + " bytes");
+  }
+  auto copy = [&](bool save) {
+    size_t o = 0;
+    for (const Piece& pc : pieces) {
+      const hipError_t r = save ? hipMemcpyAsync(keep + o, pc.dev, pc.bytes, hipMemcpyDeviceToDevice, c->stream)
+                                : hipMemcpyAsync(pc.dev, keep + o, pc.bytes, hipMemcpyDeviceToDevice, c->stream);
+      if (r != hipSuccess) return r;
+      o += (pc.bytes + 255) / 256 * 256;
+    }
+    return hipSuccess;
+  };
+  const int f0 = c->bin_factor;
+  float best_t[MAX_BIN_FACTOR + 1];
+  for (int f = 0; f <= MAX_BIN_FACTOR; ++f) best_t[f] = 1e30f;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t he = copy(true);
+  if (he == hipSuccess) he = hipEventCreate(&t0);
+  if (he == hipSuccess) he = hipEventCreate(&t1);
+  e = RCELL_OK;
+  for (int round = 0; round < 3 && he == hipSuccess && !e; ++round)
+    for (int f = 1; f <= MAX_BIN_FACTOR && he == hipSuccess && !e; ++f) {
+      if ((he = copy(false)) != hipSuccess) break;
+      // the restored cell table holds the bin offsets of the snapshot: the current layout again
+      if ((e = push_bin_layout(c)) || (e = apply_bin_factor(c, f))) break;
+      hipLaunchKernelGGL(k_set_pending, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, c->ncells);
+      if ((he = hipEventRecord(t0, c->stream)) != hipSuccess) break;
+      launch_build(c);
+      if ((he = hipEventRecord(t1, c->stream)) != hipSuccess) break;
+      if ((he = hipEventSynchronize(t1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+      best_t[f] = std::min(best_t[f], ms);
+    }
+  int best = f0;
+  if (he == hipSuccess && !e) {
+    best = 1;
+    for (int f = 2; f <= MAX_BIN_FACTOR; ++f)
+      if (best_t[f] < best_t[best]) best = f;
+    he = copy(false);                               // the state as found, then its bin layout
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  (void)hipFree(keep);
+  if (he != hipSuccess) return fail(c, RCELL_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(he));
+  if (e) return e;
+  if ((e = push_bin_layout(c)) || (e = apply_bin_factor(c, best))) return e;
+  // lanes per atom, timed on the MD step's own force pass (on copies; advances no state)
+  if ((e = rcell_set_lanes(c, 0))) return e;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = std::make_pair(c->lanes, c->bin_factor);
+  }
+  if (lanes) *lanes = c->lanes;
+  if (bin_factor) *bin_factor = c->bin_factor;
   return RCELL_OK;
 }
 

@@ -23,7 +23,7 @@ EXPORTS = ["rcell_create", "rcell_set_deformation", "rcell_set_deformation_dev",
            "rcell_get_stress", "rcell_get_stress_dev", "rcell_get_stress_ext", "rcell_destroy", "rcell_last_error",
            "rcell_get_status", "rcell_get_forces", "rcell_get_state", "rcell_set_state",
            "rcell_get_energy", "rcell_get_box", "rcell_get_rebuilds", "rcell_set_lanes",
-           "rcell_get_lanes", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps",
+           "rcell_get_lanes", "rcell_set_bin_factor", "rcell_get_bin_factor", "rcell_autotune", "rcell_prof_enable", "rcell_prof_read", "rcell_set_graph_steps",
            "rcell_qr_dev", "rcell_stress_return_dev", "rcell_minimize", "rcell_probe_peaks",
            "rcell_set_build_mode"]
 
@@ -77,6 +77,7 @@ def load():
             "rcell_set_state": [vp, i32, vp, vp, vp, vp, i64], "rcell_get_energy": [vp, vp, vp],
             "rcell_get_box": [vp, i32, vp, vp, vp, vp], "rcell_get_rebuilds": [vp, vp],
             "rcell_set_lanes": [vp, i32], "rcell_get_lanes": [vp, vp], "rcell_set_build_mode": [vp, i32],
+            "rcell_set_bin_factor": [vp, i32], "rcell_get_bin_factor": [vp, vp], "rcell_autotune": [vp, i32, vp, vp],
             "rcell_prof_enable": [vp, i32], "rcell_prof_read": [vp, i32, vp, vp],
             "rcell_set_graph_steps": [vp, i32],
             "rcell_qr_dev": [vp, i32, vp, vp, vp, vp], "rcell_stress_return_dev": [vp, vp, i32, vp, vp, vp],
@@ -252,6 +253,22 @@ class RCellBatch:
     def set_lanes(self, lanes):
         self._check(load().rcell_set_lanes(self._h, int(lanes)))
         return self.lanes()
+
+    def set_bin_factor(self, f):
+        """Neighbour bins at least (rc + skin) / f wide (f = 1 or 2), from each cell's next build."""
+        self._check(load().rcell_set_bin_factor(self._h, int(f)))
+
+    def bin_factor(self):
+        f = ctypes.c_int32(0)
+        self._check(load().rcell_get_bin_factor(self._h, ctypes.byref(f)))
+        return f.value
+
+    def autotune(self, use_cache=True):
+        """Bin factor and lanes per atom timed on this batch (the state is left as found); returns
+        (lanes, bin_factor)."""
+        l, f = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(load().rcell_autotune(self._h, 1 if use_cache else 0, ctypes.byref(l), ctypes.byref(f)))
+        return l.value, f.value
 
     def set_build_mode(self, mode):
         """0: automatic, 1: one block per cell for the rebuild preparation, 2: phase kernels."""
