@@ -72,7 +72,8 @@ typedef struct {           /* one cell, host arrays copied at create */
   int32_t nbonds;          /* number of FENE bonds (KG), 0 otherwise */
   const double* H0;        /* 9, upper triangular with positive diagonal: initial box H(0) */
   const double* x;         /* natoms*3 positions (any periodic image; wrapped into the box) */
-  const double* v;         /* natoms*3 velocities, or NULL for zero */
+  const double* v;         /* natoms*3 velocities, or NULL: Maxwell-Boltzmann at the temperature,
+                              drawn on the device from the seed (see rcell_create) */
   const int32_t* bonds;    /* nbonds*2 atom indices within the cell, or NULL; at most 4 bonds per atom */
 } rcell_cell_init;
 
@@ -82,7 +83,15 @@ typedef struct rcell_ctx rcell_ctx;
  * enqueue on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a library-owned
  * stream.  Validates the boxes (RCELL_ERR_BOX), bond lengths (RCELL_ERR_BOND) and indices, then
  * computes the initial forces and the instantaneous stress.  Before any rcell_set_deformation
- * the cells have F = Q = R = I.  On failure *out is NULL. */
+ * the cells have F = Q = R = I.  A cell given v == NULL starts from Maxwell-Boltzmann
+ * velocities: atom l of cell c takes the four words of Philox4x32-10 at counter
+ * (l, c, 0xFFFFFFFF, 0xFFFFFFFF) (a counter that the Langevin noise, whose third word is the
+ * step, never reaches), mapped to (0,1) as (w + 1/2) 2^-32, two Box-Muller pairs give its three
+ * Cartesian components (the fourth normal is unused); the cell's mean velocity is removed and the
+ * velocities are scaled so that mvv2e sum m v.v = (3 N - 3) kB T exactly.  On failure *out is NULL
+ * and everything the call allocated is freed.  For tests of that path, the environment variable
+ * RCELL_FAULT_ALLOC = k (k >= 1) makes the k-th device allocation of the call fail as if the device
+ * were out of memory (RCELL_ERR_OOM). */
 int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32_t ncells,
                  void* hip_stream, rcell_ctx** out);
 

@@ -182,8 +182,12 @@ class OracleBatch:
         self.ncells = len(cells)
         H0 = _f64(np.stack([c["H0"] for c in cells]) if cells else np.zeros((0, 3, 3)))
         x = _f64(np.concatenate([c["x"] for c in cells]) if cells else np.zeros((0, 3)))
-        v = _f64(np.concatenate([c["v"] if c.get("v") is not None else np.zeros_like(c["x"])
-                                 for c in cells]) if cells else np.zeros((0, 3)))
+        # cells without velocities: all of them draw Maxwell-Boltzmann velocities from the seed
+        no_v = [c.get("v") is None for c in cells]
+        if any(no_v) and not all(no_v):
+            raise ValueError("either every cell or no cell comes without velocities")
+        v = None if (cells and all(no_v)) else _f64(
+            np.concatenate([c["v"] for c in cells]) if cells else np.zeros((0, 3)))
         b = np.ascontiguousarray(np.concatenate(bl) if bl else np.zeros((0, 2), np.int32))
         h = ctypes.c_void_p()
         st = lib().orc_create(ctypes.byref(self._ps), self.ncells, _p(self.natoms), _p(self.nbonds),

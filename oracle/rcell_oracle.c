@@ -403,6 +403,41 @@ static void wrap_positions(ocell* c) {
   }
 }
 
+/* Initial velocities of a cell created without them: Maxwell-Boltzmann at the temperature T.  Each
+ * atom draws four uniform deviates u = (w + 1/2) 2^-32 from Philox4x32-10 (key: the seed; counter:
+ * atom index, cell index, and an all-ones step, which the Langevin noise never reaches), and the
+ * Box-Muller transform turns (u0, u1) into two and (u2, u3) into one standard normal deviate, scaled
+ * by sqrt(kB T / m).  Then the centre-of-mass velocity is subtracted, and all velocities are scaled
+ * so that sum m v^2 = (3N - 3) kB T (the equipartition value without the removed momentum). */
+static void maxwell_boltzmann(const orc_params* p, ocell* c) {
+  const uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+  const double kt_m = p->kB * p->temperature / (p->mass * p->mvv2e);
+  const double sd = sqrt(kt_m);
+  const double two_pi = 6.283185307179586476925286766559;
+  double mean[3] = {0.0, 0.0, 0.0};
+  for (int32_t i = 0; i < c->n; ++i) {
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)c->id, 0xFFFFFFFFu, 0xFFFFFFFFu}, w[4];
+    orc_philox4x32_10(ctr, key, w);
+    double u[4];
+    for (int q = 0; q < 4; ++q) u[q] = ((double)w[q] + 0.5) / 4294967296.0;
+    double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    c->v[3 * i] = sd * r0 * cos(two_pi * u[1]);
+    c->v[3 * i + 1] = sd * r0 * sin(two_pi * u[1]);
+    c->v[3 * i + 2] = sd * r1 * cos(two_pi * u[3]);
+    for (int q = 0; q < 3; ++q) mean[q] += c->v[3 * i + q];
+  }
+  double sum2 = 0.0;
+  for (int q = 0; q < 3; ++q) mean[q] /= (c->n > 0 ? c->n : 1);
+  for (int32_t i = 0; i < c->n; ++i)
+    for (int q = 0; q < 3; ++q) {
+      c->v[3 * i + q] -= mean[q];
+      sum2 += c->v[3 * i + q] * c->v[3 * i + q];
+    }
+  double scale = (c->n > 1 && sum2 > 0.0) ? sqrt(kt_m * (3.0 * c->n - 3.0) / sum2) : 0.0;
+  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->v[k] *= scale;
+}
+
+/* v == NULL: every cell starts from Maxwell-Boltzmann velocities (maxwell_boltzmann) */
 int orc_create(const orc_params* p, int32_t ncells, const int32_t* natoms, const int32_t* nbonds,
                const double* H0, const double* x, const double* v, const int32_t* bonds,
                orc_ctx** out) {
@@ -427,6 +462,7 @@ int orc_create(const orc_params* p, int32_t ncells, const int32_t* natoms, const
     if (!c->x || !c->v || !c->f || !c->bonds) { st = E_OOM; break; }
     memcpy(c->x, x + 3 * off, (size_t)c->n * 3 * sizeof(double));
     if (v) memcpy(c->v, v + 3 * off, (size_t)c->n * 3 * sizeof(double));
+    else maxwell_boltzmann(p, c);
     if (c->nb) memcpy(c->bonds, bonds + 2 * boff, (size_t)c->nb * 2 * sizeof(int32_t));
     for (int32_t b = 0; b < 2 * c->nb; ++b)
       if (c->bonds[b] < 0 || c->bonds[b] >= c->n) st = E_ARG;

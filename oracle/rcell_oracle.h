@@ -37,7 +37,7 @@ int  orc_forces(const orc_params* p, const double H[9], int32_t n, const double*
                 int32_t nbonds, const int32_t* bonds, double* f, double* pe, double vir[9]);
 
 /* batched r-cell context (same semantics as the library's create / set_deformation / run /
- * get_stress calls) */
+ * get_stress calls); v == NULL draws Maxwell-Boltzmann velocities for every cell from the seed */
 int  orc_create(const orc_params* p, int32_t ncells, const int32_t* natoms, const int32_t* nbonds,
                 const double* H0, const double* x, const double* v, const int32_t* bonds,
                 orc_ctx** out);

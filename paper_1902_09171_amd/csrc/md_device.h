@@ -964,6 +964,53 @@ __global__ __launch_bounds__(TILE) void k_start(MDArgs a) {
   write_part<TILE, 1>(a.parts, tb, Z, 0.0, false, xi, maxd2, 0, psh);
 }
 
+// ------------------------------------------------------------------ initial velocities
+// Maxwell-Boltzmann velocities for the cells created without them (flag[cell] != 0), one block of
+// MB_NT threads per cell, before the first neighbour build (atoms still in their original order):
+// three normal variates per atom by the Box-Muller transform of four Philox4x32-10 uniforms
+// u = (w + 1/2) 2^-32 (counter: atom, cell, and an all-ones step, a domain the Langevin noise never
+// reaches; key: the seed), times sqrt(kB T / m); then the centre-of-mass velocity is removed and the
+// velocities are scaled so that sum m v^2 = (3N - 3) kB T exactly.  The two sums run in a fixed tree.
+constexpr int MB_NT = 256;
+__global__ __launch_bounds__(MB_NT) void k_mb_velocities(MDArgs a, const int* flag, double sd, double dof_kt_m) {
+  __shared__ double sh[MB_NT];
+  const int c = blockIdx.x;
+  if (!flag[c]) return;                           // uniform over the block
+  const CellDev& C = a.cells[c];
+  const int n = C.n;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int l = threadIdx.x; l < n; l += MB_NT) {
+    uint32_t w[4];
+    philox((uint32_t)l, (uint32_t)c, 0xFFFFFFFFu, 0xFFFFFFFFu, a.key0, a.key1, w);
+    double u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = ((double)w[q] + 0.5) * 0x1.0p-32;
+    const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    const double t0 = 2.0 * M_PI * u[1], t1 = 2.0 * M_PI * u[3];
+    const long long i = (long long)C.off + l;
+    a.vx[i] = sd * r0 * cos(t0);
+    a.vy[i] = sd * r0 * sin(t0);
+    a.vz[i] = sd * r1 * cos(t1);
+    s[0] += a.vx[i]; s[1] += a.vy[i]; s[2] += a.vz[i];
+  }
+  double mean[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) mean[q] = block_sum<MB_NT>(s[q], sh) / (double)n;
+  double k2 = 0.0;
+  for (int l = threadIdx.x; l < n; l += MB_NT) {
+    const long long i = (long long)C.off + l;
+    const double vx = a.vx[i] - mean[0], vy = a.vy[i] - mean[1], vz = a.vz[i] - mean[2];
+    a.vx[i] = vx; a.vy[i] = vy; a.vz[i] = vz;
+    k2 += vx * vx + vy * vy + vz * vz;
+  }
+  k2 = block_sum<MB_NT>(k2, sh);
+  const double scale = (n > 1 && k2 > 0.0) ? sqrt(dof_kt_m * (double)(3 * n - 3) / k2) : 0.0;
+  for (int l = threadIdx.x; l < n; l += MB_NT) {
+    const long long i = (long long)C.off + l;
+    a.vx[i] *= scale; a.vy[i] *= scale; a.vz[i] *= scale;
+  }
+}
+
 // ------------------------------------------------------------------ molecular statics (FIRE)
 // Start of a relaxation: FIRE state of every cell, empty stress window, zero velocities.
 __global__ void k_fire_cells(CellDev* cells, int ncells, double dt) {

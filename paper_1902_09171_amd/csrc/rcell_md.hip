@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -72,6 +73,9 @@ struct rcell_ctx {
   int* iscratch = nullptr;        // ncells ints
   long long* lscratch = nullptr;  // ncells long longs
   std::vector<void*> allocs;
+  // fault injection for tests of the error paths: the fault_alloc-th device allocation of this
+  // context fails as if the device were out of memory (RCELL_FAULT_ALLOC at create; 0 = off)
+  int fault_alloc = 0, n_alloc = 0;
   // captured MD steps: graph[p] holds graph_steps middle steps starting from buffer parity p
   int graph_steps = 10;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -117,9 +121,14 @@ template <class T>
 int dalloc(rcell_ctx* c, T** out, size_t count) {
   void* p = nullptr;
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  if (c && c->fault_alloc > 0 && ++c->n_alloc == c->fault_alloc)
+    return fail(c, RCELL_ERR_OOM, "injected failure of device allocation " + std::to_string(c->n_alloc) +
+                                      " (" + std::to_string(bytes) + " bytes)");
+  const hipError_t r = hipMalloc(&p, bytes);
+  if (r != hipSuccess) {
     (void)hipGetLastError();
-    return fail(c, RCELL_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return fail(c, r == hipErrorOutOfMemory || r == hipErrorMemoryAllocation ? RCELL_ERR_OOM : RCELL_ERR_DEVICE,
+                "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(r));
   }
   c->allocs.push_back(p);
   *out = (T*)p;
@@ -592,6 +601,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
 
   rcell_ctx* c = new (std::nothrow) rcell_ctx();
   if (!c) return fail(nullptr, RCELL_ERR_OOM, "host allocation failed");
+  if (const char* fa = std::getenv("RCELL_FAULT_ALLOC")) c->fault_alloc = std::atoi(fa);
   c->p = p;
   c->fp64 = p.precision == RCELL_PREC_FP64;
   c->ncells = ncells;
@@ -642,8 +652,11 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
   if (hip_stream) {
     c->stream = (hipStream_t)hip_stream;
   } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
-      return bail(fail(c, RCELL_ERR_DEVICE, "hipStreamCreate failed"));
+    const hipError_t r = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (r != hipSuccess) {
+      c->stream = nullptr;
+      return bail(fail(c, RCELL_ERR_DEVICE, std::string("hipStreamCreate failed: ") + hipGetErrorString(r)));
+    }
     c->own_stream = true;
   }
   const size_t fsz = sizeof(double);
@@ -671,6 +684,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
 
   // ---- marshal the initial state (AoS -> SoA), bonds -> per-atom partner slots
   std::vector<double> hx(N), hy(N), hz(N), hvx(N, 0.0), hvy(N, 0.0), hvz(N, 0.0);
+  std::vector<int> mb(ncells, 0);                  // cells whose velocities are drawn on the device
   std::vector<int4> hb(N, make_int4(-1, -1, -1, -1));
   std::vector<Tile> tl;
   tl.reserve(ntiles);
@@ -683,6 +697,7 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
         return bail(fail(c, RCELL_ERR_ARG, "non-finite position in cell " + std::to_string(k)));
       if (ci.v) { hvx[o + i] = ci.v[3 * i]; hvy[o + i] = ci.v[3 * i + 1]; hvz[o + i] = ci.v[3 * i + 2]; }
     }
+    mb[k] = ci.v ? 0 : 1;
     for (int b = 0; b < ci.nbonds; ++b) {
       const int i = ci.bonds[2 * b], j = ci.bonds[2 * b + 1];
       if (i < 0 || j < 0 || i >= ci.natoms || j >= ci.natoms || i == j)
@@ -723,6 +738,14 @@ int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32
     return bail(fail(c, RCELL_ERR_DEVICE, "initial upload failed"));
   if ((e = layout_bins(c, need_bins))) return bail(e);
   hipLaunchKernelGGL(k_reset_order, dim3(tile_grid(c->ntiles)), dim3(TILE), 0, c->stream, make_args(c), 0, ncells);
+  if (std::any_of(mb.begin(), mb.end(), [](int f) { return f != 0; })) {   // Maxwell-Boltzmann from the seed
+    int* dflag = c->iscratch;
+    if (hipMemcpyAsync(dflag, mb.data(), sizeof(int) * ncells, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return bail(fail(c, RCELL_ERR_DEVICE, "velocity flags upload failed"));
+    const double sd = std::sqrt(p.kB * p.temperature / (p.mass * p.mvv2e));
+    hipLaunchKernelGGL(k_mb_velocities, dim3(ncells), dim3(MB_NT), 0, c->stream, make_args(c), (const int*)dflag, sd,
+                       p.kB * p.temperature / (p.mass * p.mvv2e));
+  }
   hipLaunchKernelGGL(k_set_box, dim3((ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, 0, ncells, bin_width(c));
   if ((e = prime(c))) return bail(e);
   Gathered g;

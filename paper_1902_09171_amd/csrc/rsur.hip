@@ -35,7 +35,10 @@ float* g_scratch_ptr[MAX_DEVICES] = {};
 // device address of the current device's scratch, looked up once per device (no allocation)
 int static_scratch_ptr(float** out) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return RCELL_ERR_DEVICE;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    (void)hipGetLastError();
+    return RCELL_ERR_DEVICE;
+  }
   std::lock_guard<std::mutex> lock(g_scratch_mu);
   if (!g_scratch_ptr[dev]) {
     void* q = nullptr;
@@ -185,7 +188,8 @@ int rsur_create(int32_t din, int32_t width, int32_t depth, int32_t dout, int32_t
   c->err.reserve(256);             // short error messages are then assigned without allocating
   {
     float* sp = nullptr;             // the static scratch's address on this device, once per device
-    if (static_scratch_ptr(&sp) != RCELL_OK) return bail(rfail(c, RCELL_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed"));
+    if (static_scratch_ptr(&sp) != RCELL_OK)
+      return bail(rfail(c, RCELL_ERR_DEVICE, "no usable HIP device (current device, or the static scratch address)"));
   }
   c->din = din; c->width = width; c->depth = depth; c->dout = dout; c->K = ensemble; c->maxB = max_batch;
   c->Mp = pad64(max_batch);
@@ -414,7 +418,7 @@ int rsur_train_step(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t B
   const long long sdz = (long long)c->Mp * dmax;
   hipLaunchKernelGGL(k_loss, dim3(LOSS_CHUNKS, c->K), dim3(LOSS_NT), 0, c->stream, c->out, sOut, c->dp[L],
                      (const float*)Y_dev, B, c->dout, c->ymu, c->ysd, c->dza, sdz, Mp, c->lpart);
-  hipLaunchKernelGGL(k_loss_total, dim3((c->K + 63) / 64), dim3(64), 0, c->stream, c->lpart, c->K, 1.0f / (float)(B * c->dout),
+  hipLaunchKernelGGL(k_loss_total, dim3((c->K + 63) / 64), dim3(64), 0, c->stream, c->lpart, c->K, 1.0f / ((float)B * (float)c->dout),
                      c->loss);
   const int S = batch_splits(Mp);
   bf16 *dz = c->dza, *dzn = c->dzb;

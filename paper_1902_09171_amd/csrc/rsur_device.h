@@ -208,18 +208,19 @@ __global__ void k_norm_in(const float* X, int B, int din, int Mp, int dp0, const
 // MSE on normalised outputs per member (one block per member, fixed order) and dLoss/dOutput
 // Loss and its output gradient: block (chunk, member) takes rows [chunk Mp / LOSS_CHUNKS, ...) of
 // one member and writes its squared-error sum to part[member][chunk] (a fixed tree over the block);
-// k_loss_total adds the chunks in order.  Mp * ldo < 2^31.
+// k_loss_total adds the chunks in order.  Element indices are 64-bit (Mp * ldo may exceed 2^31).
 constexpr int LOSS_NT = 256, LOSS_CHUNKS = 16;
 __global__ __launch_bounds__(LOSS_NT) void k_loss(const float* out, long long sOut, int ldo, const float* Y, int B,
                                                   int dout, const float* ymu, const float* ysd, bf16* dY,
                                                   long long sdY, int Mp, float* part) {
   __shared__ float sh[LOSS_NT];
   const int chunk = blockIdx.x, mem = blockIdx.y;
-  const float inv = 1.0f / (float)(B * dout);
-  const int rows = Mp / LOSS_CHUNKS, e0 = chunk * rows * ldo, e1 = e0 + rows * ldo;
+  const float inv = 1.0f / ((float)B * (float)dout);
+  const long long rows = Mp / LOSS_CHUNKS, e0 = chunk * rows * ldo, e1 = e0 + rows * ldo;
   float acc = 0.0f;
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += LOSS_NT) {
-    const int m = e / ldo, n = e - m * ldo;
+  for (long long e = e0 + (long long)threadIdx.x; e < e1; e += LOSS_NT) {
+    const long long m = e / ldo;
+    const int n = (int)(e - m * ldo);
     float gr = 0.0f;
     if (m < B && n < dout) {
       const float yn = (Y[(long long)m * dout + n] - ymu[n]) / ysd[n];

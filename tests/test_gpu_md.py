@@ -253,6 +253,47 @@ def test_errors_leave_state_untouched(rc):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_maxwell_boltzmann_velocities_match_the_oracle(rc, prec):
+    # cells created without velocities draw Maxwell-Boltzmann velocities from the seed on the
+    # device (zero total momentum, kinetic energy exactly (3N - 3) kB T / 2); the oracle draws them
+    # from the same Philox stream with the host's libm, so they agree to rounding
+    p = configs.kg_params(precision=prec)
+    cells = [dict(configs.kg_cell(lens, 4300 + k), v=None) for k, lens in enumerate(([50] * 20, [30] * 10))]
+    g = rc.RCellBatch(p, cells)
+    o = core.OracleBatch(dict(p, precision="fp64"), cells)
+    _, ke = g.get_energy()
+    for k, c in enumerate(cells):
+        vg, vo = g.get_state(k)["v"], o.get_state(k)["v"]
+        print(prec, "cell", k, "max |dv|", np.abs(vg - vo).max(), flush=True)
+        assert np.abs(vg - vo).max() <= 1e-12 * np.abs(vo).max()
+        assert np.abs(vg.sum(0)).max() <= 1e-11 * np.abs(vg).sum()
+        n = len(c["x"])
+        assert ke[k] == pytest.approx(0.5 * (3 * n - 3) * p["kB"] * p["temperature"], rel=1e-12)
+    g.get_stress()
+    o.get_stress()
+    g.run(50)
+    o.run(50)
+    check_stress(g.get_stress(), o.get_stress(), TOL[prec], key="s100", what=f"{prec} 50 steps from drawn velocities")
+
+
+def test_injected_allocation_failures_leave_nothing_behind(rc, monkeypatch):
+    # RCELL_FAULT_ALLOC=n makes the n-th device allocation of a context fail as if the device were
+    # out of memory: create must report RCELL_ERR_OOM, free what it had allocated, and a create
+    # without the fault must then work normally
+    p = configs.kg_params(precision="mixed")
+    cells = kg_cells([[20] * 10, [30] * 10], seed0=4200)
+    for n in (1, 9, 33, 37):
+        monkeypatch.setenv("RCELL_FAULT_ALLOC", str(n))
+        with pytest.raises(rc.RCellError) as e:
+            rc.RCellBatch(p, cells)
+        assert e.value.code == -6 and "injected" in str(e.value), (n, str(e.value))
+    monkeypatch.delenv("RCELL_FAULT_ALLOC")
+    g = rc.RCellBatch(p, cells)
+    g.run(20)
+    assert np.all(g.status() == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_ragged_cells_and_few_bins(rc, prec):
     # uneven cells, ragged last tiles (1000, 777, 130 atoms, 1 atom) and a box with < 3 bins per edge
     cells = kg_cells([[50] * 20, [37] * 21, [13] * 10])

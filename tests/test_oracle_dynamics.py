@@ -161,3 +161,36 @@ def test_set_deformation_is_atomic_on_error():
         ob.set_deformation(squash)
     assert e.value.code == core.ERR_BOX
     assert np.array_equal(ob.get_state(0)["x"], st_before["x"])
+
+
+def test_maxwell_boltzmann_initial_velocities():
+    """Cells created without velocities draw them from the seed: zero total momentum, kinetic energy
+    exactly (3N - 3) kB T / 2, each component normally distributed with the variance that this
+    kinetic energy leaves, components uncorrelated, reproducible for a seed and different for
+    another seed or another cell."""
+    from scipy import stats
+    p = dict(configs.kg_params(precision="fp64"), temperature=1.7, mass=2.0)
+    n_side = 28
+    g = np.arange(n_side) + 0.5
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) * 1.1      # 21952 atoms
+    H = np.eye(3) * 1.1 * n_side
+    cell = dict(x=x, v=None, bonds=np.zeros((0, 2), np.int32), H0=H)
+    small = dict(x=x[:500] * 0.5, v=None, bonds=np.zeros((0, 2), np.int32), H0=H * 0.5)
+    ob = core.OracleBatch(p, [cell, small])
+    v = ob.get_state(0)["v"]
+    n = len(v)
+    assert np.abs(v.sum(0)).max() <= 1e-11 * np.abs(v).sum()
+    ke2 = p["mass"] * (v * v).sum()
+    assert ke2 == pytest.approx((3 * n - 3) * p["kB"] * p["temperature"], rel=1e-13)
+    sd = np.sqrt(p["kB"] * p["temperature"] / p["mass"] * (3 * n - 3) / (3 * n))
+    for q in range(3):
+        assert stats.kstest(v[:, q] / sd, "norm").pvalue > 1e-3
+    c = np.corrcoef(v.T)
+    assert np.abs(c[np.triu_indices(3, 1)]).max() < 4.0 / np.sqrt(n)
+    vs = ob.get_state(1)["v"]
+    assert np.abs(vs.sum(0)).max() <= 1e-11 * np.abs(vs).sum()
+    assert not np.allclose(vs, v[:500])
+    again = core.OracleBatch(p, [cell, small]).get_state(0)["v"]
+    assert np.array_equal(again, v)
+    other = core.OracleBatch(dict(p, seed=p["seed"] + 1), [cell, small]).get_state(0)["v"]
+    assert np.abs(other - v).max() > 0.1 * sd

@@ -33,6 +33,11 @@ MUTANTS = [
     ("full kick instead of half kick", "double h = p->dt / (2.0 * p->mass * p->mvv2e);",
      "double h = p->dt / (p->mass * p->mvv2e);", "dynamics"),
     ("Philox Weyl constant", "k0 += 0x9E3779B9u;", "k0 += 0x9E3779B7u;", "philox"),
+    # the Maxwell-Boltzmann initial velocities
+    ("Box-Muller cosine for two components", "c->v[3 * i + 1] = sd * r0 * sin(two_pi * u[1]);",
+     "c->v[3 * i + 1] = sd * r0 * cos(two_pi * u[1]);", "dynamics"),
+    ("centre-of-mass velocity kept", "c->v[3 * i + q] -= mean[q];", "c->v[3 * i + q] -= 0.0 * mean[q];", "dynamics"),
+    ("3N degrees of freedom", "sqrt(kt_m * (3.0 * c->n - 3.0) / sum2)", "sqrt(kt_m * (3.0 * c->n) / sum2)", "dynamics"),
     # the cell-list branch of the pair search: bins narrower than the cutoff in a skewed box, and a
     # stencil that misses the neighbouring bin below
     ("bin count from the box edge instead of the perpendicular width",
