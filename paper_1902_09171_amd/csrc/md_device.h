@@ -88,6 +88,20 @@ __device__ __forceinline__ int block_tile(int ntiles, int block) { return block;
 __device__ __forceinline__ int block_tile_xcd(int ntiles, int block) {
   return (block % 8) * ((ntiles + 7) / 8) + block / 8;
 }
+// The same placement for block-strided loops over n work items (the rebuild phases): with a grid
+// that is a multiple of 8, XCD x runs blocks x, x + 8, ..., and they share out the contiguous item
+// range [x per, (x + 1) per), per = ceil(n / 8), so the cells that XCD rebuilds stay in its own L2.
+// A block may split its share further over sub workers (its waves): worker w of a block takes the
+// items k, k + step, ... below end.
+struct XcdLoop {
+  int k, end, step;
+  __device__ XcdLoop(int n, int sub = 1, int w = 0) {
+    const int per = (n + 7) / 8, x = (int)(blockIdx.x & 7u);
+    k = x * per + (int)(blockIdx.x >> 3) * sub + w;
+    end = min(n, (x + 1) * per);
+    step = (int)(gridDim.x >> 3) * sub;
+  }
+};
 
 struct Part {                     // one tile's contribution
   double V[6];                    // MD: pair virial minus the kinetic term; statics: the FIRE sums
@@ -1271,9 +1285,9 @@ __device__ __forceinline__ int work_tile(const MDArgs& a, int w) {
 }
 template <class Fn>
 __device__ __forceinline__ void for_work_tiles(const MDArgs& a, Fn&& fn) {
-  const int nt = a.work_count[1];
   const int lane = threadIdx.x & 63;
-  for (int k = blockIdx.x * WORK_WAVES + (threadIdx.x >> 6); k < nt; k += gridDim.x * WORK_WAVES) {
+  const XcdLoop L(a.work_count[1], WORK_WAVES, threadIdx.x >> 6);
+  for (int k = L.k; k < L.end; k += L.step) {
     const Tile t = a.tiles[work_tile(a, k)];
     if (lane < t.count) fn(t, (long long)t.begin + lane);
   }
@@ -1352,7 +1366,8 @@ __device__ __forceinline__ void scan_cell(const MDArgs& a, CellDev& C, int* sh) 
 // one block per rebuilding cell, block-strided over the work list
 __global__ __launch_bounds__(SCAN_NT) void k_bin_scan(MDArgs a) {
   __shared__ int sh[SCAN_NT / 64];
-  for (int k = blockIdx.x; k < a.work_count[0]; k += gridDim.x) scan_cell(a, a.cells[a.work_cells[k]], sh);
+  const XcdLoop L(a.work_count[0]);
+  for (int k = L.k; k < L.end; k += L.step) scan_cell(a, a.cells[a.work_cells[k]], sh);
 }
 
 // The work list of a rebuild: the cells flagged for one, in cell order, with the prefix sums of
@@ -1480,7 +1495,8 @@ __device__ __forceinline__ void sort_chunk(const MDArgs& a, const int* bin_cell,
 // one wave per 64-bin chunk of the rebuilding cells, block-strided over the work list
 __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell, int cap) {
   extern __shared__ int stage[];
-  for (int w = blockIdx.x; w < a.work_count[2]; w += gridDim.x) {
+  const XcdLoop L(a.work_count[2]);
+  for (int w = L.k; w < L.end; w += L.step) {
     __syncthreads();                 // the previous chunk's keys have been read
     const int k = work_find(a.work_kstart, a.work_count[0], w);
     const long long chunk = a.cells[a.work_cells[k]].bin_off / 64 + (w - a.work_kstart[k]);
@@ -1749,20 +1765,21 @@ __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int p
   }
 }
 
-// use_work: block-strided over the tiles of the rebuild work list; else one block per tile of the
-// batch, exiting at once for cells that do not rebuild
+// use_work: block-strided (XcdLoop) over the tiles of the rebuild work list; else one block per tile
+// of the batch (placed like the force passes), exiting at once for cells that do not rebuild
 template <class P, class LT>
 __global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a, int use_work) {
   constexpr int PER_TILE = TILE / BUILD_ATOMS;
   __shared__ int2 rng[BUILD_ATOMS][MAX_RANGES];   // candidate ranges (first position, count) per atom
   if (use_work) {
-    const int n = a.work_count[1] * PER_TILE;
-    for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const XcdLoop L(a.work_count[1] * PER_TILE);
+    for (int k = L.k; k < L.end; k += L.step) {
       __syncthreads();                           // the previous tile's ranges have been read
       build_tile<P, LT>(a, a.tiles[work_tile(a, k / PER_TILE)], k % PER_TILE, rng);
     }
   } else {
-    const int tb = block_tile(a.ntiles, blockIdx.x / PER_TILE);
+    static_assert(PER_TILE == 1, "one block per tile: the tile placement follows the block's XCD");
+    const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
     if (tb >= a.ntiles) return;
     const Tile t = a.tiles[tb];
     if (!a.cells[t.cell].rebuild) return;

@@ -321,6 +321,7 @@ void launch_reduce(rcell_ctx* c, int mode) {
 // blocks of the block-strided rebuild phases: enough to fill the GPU when many cells rebuild,
 // few enough that a step without rebuilds costs little
 constexpr int WORK_BLOCKS = 2048;
+unsigned round8(int blocks) { return (unsigned)((std::max(1, blocks) + 7) / 8 * 8); }
 
 // reduce_mode >= 0: the per-cell reduction of that mode runs first, fused into the preparation
 // launch when the cells are small enough for it
@@ -339,10 +340,10 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
     // the phases walk the work list of the cells that rebuild: small grids, block-strided
     if (reduce_mode >= 0) launch_reduce(c, reduce_mode);
     hipLaunchKernelGGL(k_rebuild_work, dim3(1), dim3(SCAN_NT), 0, c->stream, a);
-    const dim3 gw(std::max(1, std::min(WORK_BLOCKS, (c->ntiles + WORK_WAVES - 1) / WORK_WAVES))),
-        bw(TILE * WORK_WAVES);
-    const dim3 gs(std::max(1, std::min(c->ncells, WORK_BLOCKS / 8)));
-    const dim3 gk((unsigned)std::max<long long>(1, std::min<long long>(4 * WORK_BLOCKS, c->bins_total / 64)));
+    // grids of whole multiples of 8 blocks: the loops share the work out per XCD (XcdLoop)
+    const dim3 gw(round8(std::min(WORK_BLOCKS, (c->ntiles + WORK_WAVES - 1) / WORK_WAVES))), bw(TILE * WORK_WAVES);
+    const dim3 gs(round8(std::min(c->ncells, WORK_BLOCKS / 8)));
+    const dim3 gk(round8((int)std::min<long long>(4 * WORK_BLOCKS, c->bins_total / 64)));
     if (c->fp64) hipLaunchKernelGGL(k_bin<FP64>, gw, bw, 0, c->stream, a);
     else hipLaunchKernelGGL(k_bin<Mixed>, gw, bw, 0, c->stream, a);
     hipLaunchKernelGGL(k_bin_scan, gs, bc, 0, c->stream, a);
@@ -358,7 +359,7 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
     }
   }
   const int use_work = c->cell_prep ? 0 : 1;
-  const dim3 gl(use_work ? std::max(1, std::min(WORK_BLOCKS, c->ntiles * (TILE / BUILD_ATOMS)))
+  const dim3 gl(use_work ? round8(std::min(WORK_BLOCKS, c->ntiles * (TILE / BUILD_ATOMS)))
                          : tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)),
       bl(BUILD_ATOMS * LPA);
   if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a, use_work);
@@ -479,12 +480,13 @@ int ensure_list_capacity(rcell_ctx* c, int need) {
   if ((unsigned long long)need * (unsigned long long)c->npad >= (1ull << 32))
     return fail(c, RCELL_ERR_OOM, "neighbour list would exceed 2^32 entries (16 GiB); split the batch");
   drop_graphs(c);
-  dfree(c, c->nbr);
-  c->nbr = nullptr;
+  // the new list is allocated before the old one is freed: on failure the context keeps its list
+  // and its capacity
   char* q = nullptr;
   const int st = dalloc(c, &q, (size_t)need * c->npad * (c->list16 ? sizeof(uint16_t) : sizeof(int)));
-  c->nbr = q;
   if (st) return st;
+  dfree(c, c->nbr);
+  c->nbr = q;
   c->maxnb = need;
   return RCELL_OK;
 }
