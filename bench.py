@@ -681,10 +681,10 @@ def bench_fe_bar_surrogate(args, torch, rcell, configs):
     """The FE bar of fe_bar driven by the learned stress surrogate (153 -> 4 x 256 -> 6, ensemble of
     5), with batched MD as its fallback:
       (1) training data from MD-driven bars of the same mesh stepped in lockstep in one batched
-          r-cell context (2000-bead cells, 500 MD steps per load step, other imperfections and pull
-          rates), one (history, sigma_MD) pair per Gauss point per load step;
-      (2) the ensemble trained by the library's BF16 kernels; the OOD threshold is the 99th
-          percentile of the ensemble spread on held-out bars;
+          r-cell context (cells of --sur-chains x 100 beads, 500 MD steps per load step, other
+          imperfections and pull rates), one (history, sigma_MD) pair per Gauss point per load step;
+      (2) the ensemble trained by the library's BF16 kernels; the OOD threshold is the largest
+          ensemble spread met on the held-out bars;
       (3) the bar of 256 r-cells of 40 000 beads driven by the surrogate for the evaluation load
           steps, while two shadow MD batches of the same cells (two Langevin seeds) follow its
           deformation: the surrogate's stress error per Gauss point and load step against shadow MD

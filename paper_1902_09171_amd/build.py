@@ -15,6 +15,8 @@ FLAGS = [
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
+    # roctx ranges around the API calls and the phases they enqueue
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -1641,149 +1641,116 @@ __global__ __launch_bounds__(TILE) void k_reset_order(MDArgs a, int first, int c
 }
 
 // Verlet list of every atom (after the reorder, so positions are in bin order): cell-local j with
-// |d| < rc + skin over the 27 (distinct) neighbour bins.  Because the atoms are stored in bin order
-// and bins are numbered with z fastest, the three z-neighbour bins of each (x, y) column of the
-// stencil are one contiguous range of positions (two at the periodic edge in z): at most 18 ranges
-// per atom, which the atom's LPA lanes look up once into LDS.  The lanes then walk the concatenated
-// candidates interleaved - lane l takes candidates l, l + LPA, ... - so a group of lanes reads
-// consecutive positions and every lane has the same share of the work whatever the bin sizes.
-// The list is written in candidate order in the same pass (a ballot per candidate slot gives each
-// accepted candidate its index), so it is deterministic.  A block covers BUILD_ATOMS atoms, so
-// TILE / BUILD_ATOMS blocks cover one tile.
-constexpr int LPA = 8;
-constexpr int BUILD_ATOMS = 1024 / LPA < TILE ? 1024 / LPA : TILE;
+// |d| < rc + skin over the neighbour bins b - f ... b + f of every dimension (bins at least
+// (rc + skin) / f wide).  Because the atoms are stored in bin order and bins are numbered with z
+// fastest, the z-neighbour bins of each (x, y) column of the stencil are one contiguous range of
+// positions (two at the periodic edge in z).  One lane per atom walks its ranges in stencil order,
+// UNR candidates in flight, and appends every accepted one to its list: the list comes out in
+// candidate order (nearly sorted by position, so its gathers hit few cache lines) and is
+// deterministic.  A range's bounds come from the bin table while the previous range is walked.  The
+// atoms of a wave are 64 consecutive atoms of one cell, mostly of a few neighbouring bins, so at a
+// given step their lanes read the same or nearby positions.
 constexpr int MAX_BIN_FACTOR = 2;
-constexpr int STENCIL = 2 * MAX_BIN_FACTOR + 1;
-constexpr int MAX_RANGES = STENCIL * STENCIL * 2;   // columns of the stencil, each at most two ranges
-template <class P, class LT>
-__device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int part, int2 (*rng)[MAX_RANGES]) {
-  const CellDev& C = a.cells[t.cell];
-  const int slot = part * BUILD_ATOMS + threadIdx.x / LPA, lane = threadIdx.x % LPA;
-  const bool active = slot < t.count;
-  const long long i = (long long)t.begin + (active ? slot : 0);
-  const int li = (int)(i - C.off);
-  const typename P::S si = P::load(a.s_cur, i);
-  const int pk = a.abin[i];
+constexpr int BUILD_WAVES = 4;     // tiles per block of the list build, one per wave
+struct BuildGeo {                  // one atom's stencil: bins per dimension and the z ranges
+  int lo[3], cnt[3], nb[3];        // first neighbour bin (unwrapped) and count per dimension
+  int zr[2][2], nzr;               // z bins [z0, z1] of every column, or two such ranges
+  int ncol, nrange;
+};
+__device__ __forceinline__ void build_geo(const CellDev& C, int pk, int fb, BuildGeo& G) {
   const int bb[3] = {pk & BIN_MASK, (pk >> BIN_BITS) & BIN_MASK, pk >> (2 * BIN_BITS)};
-  // Neighbour bin coordinates per dimension: b - f ... b + f (periodic) for bins at least
-  // (rc + skin) / f wide (a pair within rc + skin is at most f bins apart in every dimension), or
-  // every bin when the dimension has fewer than 2 f + 1
-  const int fb = a.bin_factor;
-  int lst[3][STENCIL], cnt[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const int nbq = C.nb[q];
-    if (nbq >= 2 * fb + 1) {
-      cnt[q] = 2 * fb + 1;
-      for (int k = 0; k <= 2 * fb; ++k) {
-        const int v = bb[q] - fb + k;
-        lst[q][k] = v < 0 ? v + nbq : (v >= nbq ? v - nbq : v);
-      }
-    } else {
-      cnt[q] = nbq;
-      for (int k = 0; k < STENCIL; ++k) lst[q][k] = k;
-    }
+    G.nb[q] = C.nb[q];
+    // a pair within rc + skin is at most f bins apart in every dimension; a dimension with fewer
+    // than 2 f + 1 bins is scanned whole
+    if (G.nb[q] >= 2 * fb + 1) { G.lo[q] = bb[q] - fb; G.cnt[q] = 2 * fb + 1; }
+    else { G.lo[q] = 0; G.cnt[q] = G.nb[q]; }
   }
+  const int nbz = G.nb[2];
+  G.zr[0][0] = 0; G.zr[0][1] = nbz - 1; G.zr[1][0] = 0; G.zr[1][1] = 0; G.nzr = 1;
+  if (nbz >= 2 * fb + 1) {
+    const int lo = bb[2] - fb, hi = bb[2] + fb;
+    if (lo < 0) { G.zr[0][0] = 0; G.zr[0][1] = hi; G.zr[1][0] = lo + nbz; G.zr[1][1] = nbz - 1; G.nzr = 2; }
+    else if (hi >= nbz) { G.zr[0][0] = lo; G.zr[0][1] = nbz - 1; G.zr[1][0] = 0; G.zr[1][1] = hi - nbz; G.nzr = 2; }
+    else { G.zr[0][0] = lo; G.zr[0][1] = hi; }
+  }
+  G.ncol = G.cnt[0] * G.cnt[1];
+  G.nrange = G.ncol * G.nzr;
+}
+// range r of the stencil (column-major over x, y, then the z parts): first position and count
+__device__ __forceinline__ int2 build_range(const MDArgs& a, const CellDev& C, const BuildGeo& G, int r) {
+  const int col = r / G.nzr, part = r - col * G.nzr;
+  const int u0 = col / G.cnt[1], u1 = col - u0 * G.cnt[1];
+  int x = G.lo[0] + u0, y = G.lo[1] + u1;
+  x = x < 0 ? x + G.nb[0] : (x >= G.nb[0] ? x - G.nb[0] : x);
+  y = y < 0 ? y + G.nb[1] : (y >= G.nb[1] ? y - G.nb[1] : y);
+  const int bc = C.bin_off + (x * G.nb[1] + y) * G.nb[2];
+  const int bf = bc + G.zr[part][0], bl = bc + G.zr[part][1];
+  const int beg = a.bstart[bf];
+  return make_int2(beg, a.bstart[bl] + a.bnum[bl] - beg);
+}
+template <class P, class LT>
+__device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int slot) {
+  if (slot >= t.count) return;
+  const CellDev& C = a.cells[t.cell];
+  const long long i = (long long)t.begin + slot;
+  const int li = (int)(i - C.off);
+  const typename P::S si = P::load(a.s_cur, i);
+  BuildGeo G;
+  build_geo(C, a.abin[i], a.bin_factor, G);
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
   const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
-  // z part of every column: bins [z0, z1], or two such ranges across the periodic edge
-  const int nbz = C.nb[2];
-  int zr[2][2] = {{0, nbz - 1}, {0, 0}}, nzr = 1;
-  if (nbz >= 2 * fb + 1) {
-    const int lo = bb[2] - fb, hi = bb[2] + fb;
-    if (lo < 0) { zr[0][0] = 0; zr[0][1] = hi; zr[1][0] = lo + nbz; zr[1][1] = nbz - 1; nzr = 2; }
-    else if (hi >= nbz) { zr[0][0] = lo; zr[0][1] = nbz - 1; zr[1][0] = 0; zr[1][1] = hi - nbz; nzr = 2; }
-    else { zr[0][0] = lo; zr[0][1] = hi; }
-  }
-  const int nrange = cnt[0] * cnt[1] * nzr;
-  int2* rg = rng[threadIdx.x / LPA];
-  for (int r = lane; r < nrange; r += LPA) {
-    const int col = r / nzr, part = r - col * nzr;
-    const int u0 = col / cnt[1], u1 = col - u0 * cnt[1];
-    const int bc = C.bin_off + (lst[0][u0] * C.nb[1] + lst[1][u1]) * nbz;
-    const int bf = bc + zr[part][0], bl = bc + zr[part][1];
-    const int beg = a.bstart[bf];
-    rg[r] = make_int2(beg, a.bstart[bl] + a.bnum[bl] - beg);
-  }
-  __syncthreads();
-  // Walk this lane's candidates, UNR in flight.  For each candidate slot the atom's lanes take a
-  // ballot of the accepted ones and write them at the running count plus the accepted lanes below
-  // them, so the list comes out in candidate order (neighbours that sit next to each other in
-  // memory are next to each other in the list) in a single pass.
+  LT* const list = (LT*)a.nbr;
   const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
-  const unsigned gshift = (threadIdx.x & 63u) & ~(unsigned)(LPA - 1), below = (1u << lane) - 1u;
+  const int cap = a.maxnb;
   int count = 0;
-  if (active && nrange > 0) {
-    int r = 0, off = 0;                       // range r holds candidates [off, off + cur.y)
-    int2 cur = rg[0];
-    for (int c0 = lane;; c0 += UNR * LPA) {
+  int2 cur = build_range(a, C, G, 0);
+  for (int r = 0; r < G.nrange; ++r) {
+    const int2 nxt = r + 1 < G.nrange ? build_range(a, C, G, r + 1) : make_int2(0, 0);
+    for (int p = 0; p < cur.y; p += UNR) {
       int pos[UNR];
-      bool ok[UNR];
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int c = c0 + u * LPA;
-        while (r < nrange && c >= off + cur.y) {
-          off += cur.y;
-          if (++r < nrange) cur = rg[r];
-        }
-        ok[u] = r < nrange;
-        pos[u] = ok[u] ? cur.x + (c - off) : li;
-      }
-      if (!ok[0]) break;
       typename P::S sj[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, pos[u]);
+      for (int u = 0; u < UNR; ++u) {
+        pos[u] = p + u < cur.y ? cur.x + p + u : li;
+        sj[u] = P::load_rel(sc, pos[u]);
+      }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        bool acc = false;
-        if (ok[u] && pos[u] != li) {
-          typename P::R d[3];
-          P::sep(sj[u], si, g, d);
-          acc = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2;
+        typename P::R d[3];
+        P::sep(sj[u], si, g, d);
+        if (pos[u] != li && d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
+          if (count < cap) list[list_index((unsigned)count, np, ii)] = (LT)pos[u];
+          ++count;
         }
-        const unsigned gm = (unsigned)(__ballot(acc) >> gshift) & ((1u << LPA) - 1u);
-        if (acc) {
-          const int k = count + __popc(gm & below);
-          if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii)] = (LT)pos[u];
-        }
-        count += __popc(gm);
       }
-      if (!ok[UNR - 1]) break;
     }
+    cur = nxt;
   }
-  // the atom's total: its lanes stop counting when their own candidates end, so take the largest
-  int n = count;
-#pragma unroll
-  for (int o = 1; o < LPA; o <<= 1) n = max(n, __shfl_xor(n, o, LPA));
-  if (active && lane == 0) {
-    if (n > a.maxnb) {
-      atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
-      n = a.maxnb;
-    }
-    a.nn[i] = n;
+  if (count > cap) {
+    atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
+    count = cap;
   }
+  a.nn[i] = count;
 }
 
-// use_work: block-strided (XcdLoop) over the tiles of the rebuild work list; else one block per tile
-// of the batch (placed like the force passes), exiting at once for cells that do not rebuild
+// use_work: the tiles of the rebuild work list, one per wave, block-strided (XcdLoop); else one
+// wave per tile of the batch (placed like the force passes), exiting at once for cells that do not
+// rebuild
 template <class P, class LT>
-__global__ __launch_bounds__(BUILD_ATOMS * LPA) void k_build_list(MDArgs a, int use_work) {
-  constexpr int PER_TILE = TILE / BUILD_ATOMS;
-  __shared__ int2 rng[BUILD_ATOMS][MAX_RANGES];   // candidate ranges (first position, count) per atom
+__global__ __launch_bounds__(TILE * BUILD_WAVES) void k_build_list(MDArgs a, int use_work) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (use_work) {
-    const XcdLoop L(a.work_count[1] * PER_TILE);
-    for (int k = L.k; k < L.end; k += L.step) {
-      __syncthreads();                           // the previous tile's ranges have been read
-      build_tile<P, LT>(a, a.tiles[work_tile(a, k / PER_TILE)], k % PER_TILE, rng);
-    }
+    const XcdLoop L(a.work_count[1], BUILD_WAVES, wave);
+    for (int k = L.k; k < L.end; k += L.step) build_tile<P, LT>(a, a.tiles[work_tile(a, k)], lane);
   } else {
-    static_assert(PER_TILE == 1, "one block per tile: the tile placement follows the block's XCD");
     const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
-    if (tb >= a.ntiles) return;
+    if (tb >= a.ntiles || wave != 0) return;
     const Tile t = a.tiles[tb];
     if (!a.cells[t.cell].rebuild) return;
-    build_tile<P, LT>(a, t, blockIdx.x % PER_TILE, rng);
+    build_tile<P, LT>(a, t, lane);
   }
 }
 

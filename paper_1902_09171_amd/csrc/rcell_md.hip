@@ -3,6 +3,7 @@
 // the method runs in the kernels of md_device.h.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -24,6 +25,15 @@ using namespace rcell;
 namespace {
 
 thread_local std::string g_create_error;
+
+// A roctx range over a scope: every API call and every phase it enqueues shows up as a named range
+// in a marker trace (rocprofv3 --marker-trace); without a profiler the calls cost a few ns.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 }  // namespace
 
@@ -310,6 +320,7 @@ void launch_force_args(rcell_ctx* c, const MDArgs& a, int mode, int l) {
 }
 
 void launch_force(rcell_ctx* c, int mode, int lanes = -1) {
+  TraceRange tr(mode == MODE_STEP ? "rcell: force pass + integration" : "rcell: force pass");
   launch_force_args(c, make_args(c), mode, lanes > 0 ? lanes : c->lanes);
 }
 
@@ -326,6 +337,7 @@ unsigned round8(int blocks) { return (unsigned)((std::max(1, blocks) + 7) / 8 * 
 // reduce_mode >= 0: the per-cell reduction of that mode runs first, fused into the preparation
 // launch when the cells are small enough for it
 void launch_build(rcell_ctx* c, int reduce_mode = -1) {
+  TraceRange tr("rcell: reduce + neighbour rebuild");
   const MDArgs a = make_args(c);
   const dim3 gt(tile_grid(c->ntiles)), bt(TILE), gc(c->ncells), bc(SCAN_NT);
   if (c->cell_prep) {              // small cells: the six preparation phases in one launch
@@ -359,9 +371,9 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
     }
   }
   const int use_work = c->cell_prep ? 0 : 1;
-  const dim3 gl(use_work ? round8(std::min(WORK_BLOCKS, c->ntiles * (TILE / BUILD_ATOMS)))
-                         : tile_grid(c->ntiles) * (TILE / BUILD_ATOMS)),
-      bl(BUILD_ATOMS * LPA);
+  const dim3 gl(use_work ? round8(std::min(WORK_BLOCKS, (c->ntiles + BUILD_WAVES - 1) / BUILD_WAVES))
+                         : tile_grid(c->ntiles)),
+      bl(use_work ? TILE * BUILD_WAVES : TILE);
   if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a, use_work);
   else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a, use_work);
   else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a, use_work);
@@ -505,6 +517,7 @@ void destroy_all(rcell_ctx* c) {
 }
 
 int deformation_common(rcell_ctx* c, const double* F_dev) {
+  TraceRange tr("rcell_set_deformation");
   const int nc = c->ncells;
   const double rcs = c->p.rc + c->p.skin;
   hipLaunchKernelGGL(k_qr_stage, dim3((nc + 63) / 64), dim3(64), 0, c->stream, F_dev, c->cells, c->stage, nc, rcs,
@@ -584,6 +597,7 @@ extern "C" {
 
 int rcell_create(const rcell_params* params, const rcell_cell_init* cells, int32_t ncells, void* hip_stream,
                  rcell_ctx** out) {
+  TraceRange tr("rcell_create");
   if (!out) return fail(nullptr, RCELL_ERR_ARG, "out is NULL");
   *out = nullptr;
   if (!params || !cells || ncells < 1) return fail(nullptr, RCELL_ERR_ARG, "params, cells and ncells >= 1 are required");
@@ -801,6 +815,7 @@ static int capture_graph(rcell_ctx* c) {
 int rcell_run(rcell_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return c ? fail(c, RCELL_ERR_ARG, "nsteps < 0") : RCELL_ERR_ARG;
   if (nsteps == 0) return RCELL_OK;
+  TraceRange tr("rcell_run");
   launch_start(c);
   launch_build(c, RED_START);
   int left = nsteps - 1;                           // middle steps; the last step ends the run
@@ -810,7 +825,10 @@ int rcell_run(rcell_ctx* c, int32_t nsteps) {
       const int e = capture_graph(c);
       if (e) return e;
     }
-    HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+    {
+      TraceRange tg("rcell: graph replay of middle steps");
+      HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+    }
     left -= c->graph_steps;                        // an even number of swaps: parity unchanged
   }
   for (; left > 0; --left) middle_step(c);
@@ -821,6 +839,7 @@ int rcell_run(rcell_ctx* c, int32_t nsteps) {
 }
 
 static int stress_out(rcell_ctx* c, void* sigma_dev, void* P_dev, void* smd_dev) {
+  TraceRange tr("rcell: stress return");
   hipLaunchKernelGGL(k_stress_out, dim3((c->ncells + 63) / 64), dim3(64), 0, c->stream, c->cells, c->ncells,
                      (double*)sigma_dev, (double*)P_dev, (double*)smd_dev);
   HIPCHK(c, hipGetLastError());
@@ -871,6 +890,7 @@ int rcell_destroy(rcell_ctx* c) {
 const char* rcell_last_error(const rcell_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 int rcell_minimize(rcell_ctx* c, int32_t max_iter, double ftol, int32_t* iters) {
+  TraceRange tr("rcell_minimize");
   if (!c) return RCELL_ERR_ARG;
   if (max_iter < 0 || !(ftol > 0) || !std::isfinite(ftol)) return fail(c, RCELL_ERR_ARG, "max_iter >= 0 and ftol > 0");
   const int nc = c->ncells;
@@ -1124,6 +1144,7 @@ int rcell_get_bin_factor(rcell_ctx* c, int32_t* f) {
 }
 
 int rcell_autotune(rcell_ctx* c, int32_t use_cache, int32_t* lanes, int32_t* bin_factor) {
+  TraceRange tr("rcell_autotune");
   if (!c) return RCELL_ERR_ARG;
   const auto key = tune_key(c);
   int e;

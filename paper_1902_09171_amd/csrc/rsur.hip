@@ -2,6 +2,7 @@
 // flat parameter layout to the padded device layout, and the launch sequence of inference and
 // of one training step.  The arithmetic runs in the kernels of rsur_device.h.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -18,6 +19,14 @@ using namespace rsur;
 
 namespace {
 thread_local std::string g_rsur_create_error;
+
+// A roctx range over a scope (rocprofv3 --marker-trace names each call; a few ns without a profiler)
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 }
 
 // Scratch of rsur_forward_static: every member's output for the rows of one call (K x pad64(B) x
@@ -379,11 +388,13 @@ static int forward_common(rsur_ctx* c, const void* X_dev, int32_t B, float* mean
 }
 
 int rsur_forward(rsur_ctx* c, const void* X_dev, int32_t B, void* mean_dev, void* var_dev) {
+  TraceRange tr("rsur_forward");
   if (!c || !X_dev || !mean_dev) return c ? rfail(c, RCELL_ERR_ARG, "NULL pointer") : RCELL_ERR_ARG;
   return forward_common(c, X_dev, B, (float*)mean_dev, (float*)var_dev, nullptr);
 }
 
 int rsur_forward_static(rsur_ctx* c, const void* X_dev, int32_t B, void* mean_dev, void* var_dev) {
+  TraceRange tr("rsur_forward_static");
   if (!c || !X_dev || !mean_dev) return c ? rfail(c, RCELL_ERR_ARG, "NULL pointer") : RCELL_ERR_ARG;
   if (!fused_shape(c)) return rfail(c, RCELL_ERR_ARG, "static forward: padded widths <= 256, <= 8 layers");
   if (B < 1 || (long long)c->K * pad64(B) * c->dp[c->L] > RSUR_STATIC_FLOATS)
@@ -406,6 +417,7 @@ int rsur_forward_members(rsur_ctx* c, const void* X_dev, int32_t B, void* out_de
 }
 
 int rsur_train_step(rsur_ctx* c, const void* X_dev, const void* Y_dev, int32_t B, float lr, float* loss) {
+  TraceRange tr("rsur_train_step");
   if (!c || !X_dev || !Y_dev || !(lr > 0)) return c ? rfail(c, RCELL_ERR_ARG, "bad train_step arguments") : RCELL_ERR_ARG;
   int e = check_batch(c, B);
   if (e) return e;
