@@ -1241,8 +1241,27 @@ __global__ __launch_bounds__(RED_NT) void k_reduce(MDArgs a, int mode) {
 //   k_bin_fill   scatter of cell-local indices into their bins (tiles)
 //   k_bin_sort   order every bin by atom index (one thread per bin), so that the neighbour lists
 //                and the force sums built from them are deterministic
+// atomicAdd(ctr + key, 1) for every valid lane of the wave, one atomic per run of equal keys in
+// consecutive lanes: the atoms of a tile are stored in bin order from the last build and have
+// mostly stayed in their bins, so neighbouring lanes usually share a key.  The run's first lane
+// adds the run length and shares the old value; a lane's slot is that value plus its rank in the
+// run (distinct slots, as with one atomic per lane).  Every lane of the wave calls this.
+__device__ __forceinline__ int wave_run_add(int* ctr, int key, bool valid) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int pkey = __shfl_up(key, 1), pvalid = __shfl_up((int)valid, 1);
+  const bool brk = !valid || lane == 0 || !pvalid || pkey != key;
+  const unsigned long long breaks = __ballot(brk);
+  const unsigned long long le = (2ull << lane) - 1ull;           // lanes <= this one (all for 63)
+  const int head = 63 - __clzll(breaks & le);
+  const unsigned long long gt = breaks & ~le;
+  const int end = gt ? __ffsll((long long)gt) - 1 : 64;
+  int old = 0;
+  if (valid && head == lane) old = atomicAdd(ctr + key, end - lane);
+  return __shfl(old, head) + (lane - head);
+}
+
 template <class P>
-__device__ __forceinline__ void bin_atom(const MDArgs& a, const CellDev& C, long long i) {
+__device__ __forceinline__ int bin_one(const MDArgs& a, const CellDev& C, long long i) {
   double x = a.x[i], y = a.y[i], z = a.z[i];
   const double s0 = C.Hi[0] * x + C.Hi[1] * y + C.Hi[2] * z, s1 = C.Hi[4] * y + C.Hi[5] * z, s2 = C.Hi[8] * z;
   const double k0 = floor(s0), k1 = floor(s1), k2 = floor(s2);
@@ -1262,7 +1281,14 @@ __device__ __forceinline__ void bin_atom(const MDArgs& a, const CellDev& C, long
   for (int q = 0; q < 3; ++q) b[q] = min((int)(f[q] * C.nb[q]), C.nb[q] - 1);
   const int bin = (b[0] * C.nb[1] + b[1]) * C.nb[2] + b[2];
   a.abin[i] = b[0] | (b[1] << BIN_BITS) | (b[2] << (2 * BIN_BITS));   // packed bin coordinates
-  atomicAdd(&a.bcount[C.bin_off + bin], 1);
+  return bin;
+}
+
+template <class P>
+__device__ __forceinline__ void bin_atom(const MDArgs& a, const CellDev& C, long long i, bool valid) {
+  int bin = -1;
+  if (valid) bin = bin_one<P>(a, C, i);
+  (void)wave_run_add(a.bcount + C.bin_off, bin, valid);
 }
 
 // Tile phases of a rebuild walk the work list: WORK_WAVES tiles per block, one wave per tile,
@@ -1292,10 +1318,21 @@ __device__ __forceinline__ void for_work_tiles(const MDArgs& a, Fn&& fn) {
     if (lane < t.count) fn(t, (long long)t.begin + lane);
   }
 }
+// the same walk with every lane of the wave calling fn (valid: the lane holds an atom of the tile)
+template <class Fn>
+__device__ __forceinline__ void for_work_tiles_wave(const MDArgs& a, Fn&& fn) {
+  const int lane = threadIdx.x & 63;
+  const XcdLoop L(a.work_count[1], WORK_WAVES, threadIdx.x >> 6);
+  for (int k = L.k; k < L.end; k += L.step) {
+    const Tile t = a.tiles[work_tile(a, k)];
+    const bool valid = lane < t.count;
+    fn(t, (long long)t.begin + (valid ? lane : 0), valid);
+  }
+}
 
 template <class P>
 __global__ __launch_bounds__(TILE * WORK_WAVES) void k_bin(MDArgs a) {
-  for_work_tiles(a, [&](const Tile& t, long long i) { bin_atom<P>(a, a.cells[t.cell], i); });
+  for_work_tiles_wave(a, [&](const Tile& t, long long i, bool valid) { bin_atom<P>(a, a.cells[t.cell], i, valid); });
 }
 
 // The displacement threshold for displacements measured against the 16-bit build reference: a
@@ -1405,15 +1442,18 @@ __global__ __launch_bounds__(SCAN_NT) void k_rebuild_work(MDArgs a) {
   }
 }
 
-__device__ __forceinline__ void fill_atom(const MDArgs& a, const CellDev& C, long long i) {
-  const int pk = a.abin[i];
-  const int bin = ((pk & BIN_MASK) * C.nb[1] + ((pk >> BIN_BITS) & BIN_MASK)) * C.nb[2] + (pk >> (2 * BIN_BITS));
-  const int slot = atomicAdd(&a.bfill[C.bin_off + bin], 1);
-  a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
+__device__ __forceinline__ void fill_atom(const MDArgs& a, const CellDev& C, long long i, bool valid) {
+  int bin = -1;
+  if (valid) {
+    const int pk = a.abin[i];
+    bin = ((pk & BIN_MASK) * C.nb[1] + ((pk >> BIN_BITS) & BIN_MASK)) * C.nb[2] + (pk >> (2 * BIN_BITS));
+  }
+  const int slot = wave_run_add(a.bfill + C.bin_off, bin, valid);
+  if (valid) a.binned[C.off + a.bstart[C.bin_off + bin] + slot] = (int)(i - C.off);
 }
 
 __global__ __launch_bounds__(TILE * WORK_WAVES) void k_bin_fill(MDArgs a) {
-  for_work_tiles(a, [&](const Tile& t, long long i) { fill_atom(a, a.cells[t.cell], i); });
+  for_work_tiles_wave(a, [&](const Tile& t, long long i, bool valid) { fill_atom(a, a.cells[t.cell], i, valid); });
 }
 
 // one lane per bin slot of every cell (grid over the bin capacity), one wave per block.  Each bin
@@ -1507,7 +1547,8 @@ __global__ __launch_bounds__(64) void k_bin_sort(MDArgs a, const int* bin_cell, 
 // Reorder the atoms of every rebuilding cell by (bin, original index): position q of the cell
 // receives the atom binned[q].  Phase 1 gathers positions, velocities, the fixed-point coordinates,
 // bin coordinates and original indices into the scratch rows and records pos_of; phase 2 copies
-// them back (also as the build reference) and rewrites the bond partners from bond0 through pos_of.
+// them back (also as the build reference) and rewrites the bond partners from bond0 through pos_of
+// (inside the list build, or as the last phase of the one-block-per-cell preparation).
 // The stored total force is not moved: the prime or last step of the run writes it afterwards.
 template <class P>
 struct Reorder {
@@ -1565,10 +1606,6 @@ __device__ __forceinline__ void reorder_scatter_atom(const MDArgs& a, const Cell
               b0.z < 0 ? self : a.pos_of[C.off + b0.z], b0.w < 0 ? self : a.pos_of[C.off + b0.w]);
 }
 
-template <class P>
-__global__ __launch_bounds__(TILE * WORK_WAVES) void k_reorder_scatter(MDArgs a) {
-  for_work_tiles(a, [&](const Tile& t, long long i) { reorder_scatter_atom<P>(a, a.cells[t.cell], i); });
-}
 
 // The six preparation phases of a rebuild (bin, scan, fill, sort, reorder gather and scatter) for
 // cells of at most PREP_ATOMS atoms: one block per cell runs them in turn, separated by block
@@ -1580,10 +1617,16 @@ template <class P>
 __device__ __forceinline__ void prep_cell(const MDArgs& a, int cell, int* sh, int* key) {
   CellDev& C = a.cells[cell];
   const int n = C.n, t = threadIdx.x;
-  for (int l = t; l < n; l += SCAN_NT) bin_atom<P>(a, C, (long long)C.off + l);
+  for (int l0 = 0; l0 < n; l0 += SCAN_NT) {     // whole waves: the bin counts aggregate over lanes
+    const bool v = l0 + t < n;
+    bin_atom<P>(a, C, (long long)C.off + (v ? l0 + t : 0), v);
+  }
   __syncthreads();
   scan_cell(a, C, sh);                       // ends with a barrier
-  for (int l = t; l < n; l += SCAN_NT) fill_atom(a, C, (long long)C.off + l);
+  for (int l0 = 0; l0 < n; l0 += SCAN_NT) {
+    const bool v = l0 + t < n;
+    fill_atom(a, C, (long long)C.off + (v ? l0 + t : 0), v);
+  }
   __syncthreads();
   for (int q = t; q < n; q += SCAN_NT) key[q] = a.gid[C.off + a.binned[C.off + q]];
   __syncthreads();
@@ -1690,18 +1733,25 @@ __device__ __forceinline__ int2 build_range(const MDArgs& a, const CellDev& C, c
   const int beg = a.bstart[bf];
   return make_int2(beg, a.bstart[bl] + a.bnum[bl] - beg);
 }
-template <class P, class LT>
+// SCATTER: the reorder's second half for this atom happens here (its row copied from the reorder
+// scratch to the per-atom arrays, bond partners renumbered), and the candidates are read from the
+// scratch, which holds the same reordered coordinates: no other lane reads the arrays being written,
+// and the rebuild needs one launch fewer.
+template <class P, class LT, bool SCATTER>
 __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int slot) {
   if (slot >= t.count) return;
   const CellDev& C = a.cells[t.cell];
   const long long i = (long long)t.begin + slot;
   const int li = (int)(i - C.off);
-  const typename P::S si = P::load(a.s_cur, i);
+  const Reorder<P> ro(a);
+  if constexpr (SCATTER) reorder_scatter_atom<P>(a, C, i);
+  const typename P::S* sbase = SCATTER ? (const typename P::S*)ro.s : (const typename P::S*)a.s_cur;
+  const typename P::S si = sbase[i];
   BuildGeo G;
-  build_geo(C, a.abin[i], a.bin_factor, G);
+  build_geo(C, SCATTER ? ro.abin[i] : a.abin[i], a.bin_factor, G);
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
-  const typename P::S* sc = (const typename P::S*)a.s_cur + C.off;
+  const typename P::S* sc = sbase + C.off;
   LT* const list = (LT*)a.nbr;
   const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
   const int cap = a.maxnb;
@@ -1736,21 +1786,117 @@ __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int s
   a.nn[i] = count;
 }
 
-// use_work: the tiles of the rebuild work list, one per wave, block-strided (XcdLoop); else one
-// wave per tile of the batch (placed like the force passes), exiting at once for cells that do not
-// rebuild
+// use_work: the tiles of the rebuild work list, one per wave, block-strided (XcdLoop), with the
+// reorder's scatter fused in; else (the one-block-per-cell preparation has done the whole reorder)
+// one wave per tile of the batch, placed like the force passes, exiting at once for cells that do
+// not rebuild
+// Rebuild sets of fewer than BUILD_SPLIT tiles leave most of the GPU idle with one lane per atom;
+// there k_build_list_lanes builds the same lists with BUILD_LPA lanes per atom (below).
+constexpr int BUILD_SPLIT = 4096;
 template <class P, class LT>
 __global__ __launch_bounds__(TILE * BUILD_WAVES) void k_build_list(MDArgs a, int use_work) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (use_work) {
+    if (a.work_count[1] < BUILD_SPLIT) return;
     const XcdLoop L(a.work_count[1], BUILD_WAVES, wave);
-    for (int k = L.k; k < L.end; k += L.step) build_tile<P, LT>(a, a.tiles[work_tile(a, k)], lane);
+    for (int k = L.k; k < L.end; k += L.step) build_tile<P, LT, true>(a, a.tiles[work_tile(a, k)], lane);
   } else {
     const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
     if (tb >= a.ntiles || wave != 0) return;
     const Tile t = a.tiles[tb];
     if (!a.cells[t.cell].rebuild) return;
-    build_tile<P, LT>(a, t, lane);
+    build_tile<P, LT, false>(a, t, lane);
+  }
+}
+
+// The same lists for small rebuild sets, BUILD_LPA lanes per atom: the atom's ranges are looked up
+// once into LDS, its lanes walk the concatenated candidates interleaved (lane l takes candidates l,
+// l + BUILD_LPA, ...), and for each candidate slot a ballot over the atom's lanes gives every
+// accepted candidate its index (the running count plus the accepted lanes below), so the list
+// comes out in the same candidate order as with one lane per atom.  The reorder's scatter is fused
+// in as in k_build_list (the atom's first lane copies its row).
+constexpr int BUILD_LPA = 8;
+constexpr int MAX_RANGES = (2 * MAX_BIN_FACTOR + 1) * (2 * MAX_BIN_FACTOR + 1) * 2;
+template <class P, class LT>
+__device__ __forceinline__ void build_tile_lanes(const MDArgs& a, const Tile& t, int2 (*rng)[MAX_RANGES]) {
+  const int slot = threadIdx.x / BUILD_LPA, lane = threadIdx.x % BUILD_LPA;
+  const bool active = slot < t.count;
+  const CellDev& C = a.cells[t.cell];
+  const long long i = (long long)t.begin + (active ? slot : 0);
+  const int li = (int)(i - C.off);
+  const Reorder<P> ro(a);
+  if (active && lane == 0) reorder_scatter_atom<P>(a, C, i);
+  const typename P::S* sc = (const typename P::S*)ro.s + C.off;
+  const typename P::S si = sc[li];
+  BuildGeo G;
+  build_geo(C, ro.abin[i], a.bin_factor, G);
+  int2* rg = rng[slot];
+  for (int r = lane; r < G.nrange; r += BUILD_LPA) rg[r] = build_range(a, C, G, r);
+  __syncthreads();
+  const typename P::R rcs2 = (typename P::R)a.rcs2;
+  const typename P::Geo g = P::geo(C);
+  const unsigned np = (unsigned)a.npad, ii = (unsigned)i;
+  const unsigned gshift = (threadIdx.x & 63u) & ~(unsigned)(BUILD_LPA - 1), below = (1u << lane) - 1u;
+  int count = 0;
+  if (active && G.nrange > 0) {
+    int r = 0, off = 0;                       // range r holds candidates [off, off + cur.y)
+    int2 cur = rg[0];
+    for (int c0 = lane;; c0 += UNR * BUILD_LPA) {
+      int pos[UNR];
+      bool ok[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int c = c0 + u * BUILD_LPA;
+        while (r < G.nrange && c >= off + cur.y) {
+          off += cur.y;
+          if (++r < G.nrange) cur = rg[r];
+        }
+        ok[u] = r < G.nrange;
+        pos[u] = ok[u] ? cur.x + (c - off) : li;
+      }
+      if (!ok[0]) break;
+      typename P::S sj[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) sj[u] = P::load_rel(sc, pos[u]);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        bool acc = false;
+        if (ok[u] && pos[u] != li) {
+          typename P::R d[3];
+          P::sep(sj[u], si, g, d);
+          acc = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2;
+        }
+        const unsigned gm = (unsigned)(__ballot(acc) >> gshift) & ((1u << BUILD_LPA) - 1u);
+        if (acc) {
+          const int k = count + __popc(gm & below);
+          if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii)] = (LT)pos[u];
+        }
+        count += __popc(gm);
+      }
+      if (!ok[UNR - 1]) break;
+    }
+  }
+  // the atom's total: its lanes stop counting when their own candidates end, so take the largest
+  int n = count;
+#pragma unroll
+  for (int o = 1; o < BUILD_LPA; o <<= 1) n = max(n, __shfl_xor(n, o, BUILD_LPA));
+  if (active && lane == 0) {
+    if (n > a.maxnb) {
+      atomicMin(&a.cells[t.cell].status, (int)ST_CAP);
+      n = a.maxnb;
+    }
+    a.nn[i] = n;
+  }
+}
+
+template <class P, class LT>
+__global__ __launch_bounds__(TILE * BUILD_LPA) void k_build_list_lanes(MDArgs a) {
+  __shared__ int2 rng[TILE][MAX_RANGES];      // candidate ranges (first position, count) per atom
+  if (a.work_count[1] >= BUILD_SPLIT) return;
+  const XcdLoop L(a.work_count[1]);
+  for (int k = L.k; k < L.end; k += L.step) {
+    __syncthreads();                          // the previous tile's ranges have been read
+    build_tile_lanes<P, LT>(a, a.tiles[work_tile(a, k)], rng);
   }
 }
 

@@ -362,13 +362,9 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
     hipLaunchKernelGGL(k_bin_fill, gw, bw, 0, c->stream, a);
     hipLaunchKernelGGL(k_bin_sort, gk, dim3(64), sizeof(int) * c->sort_cap, c->stream, a,
                        (const int*)c->bin_cell, c->sort_cap);
-    if (c->fp64) {
-      hipLaunchKernelGGL(k_reorder_gather<FP64>, gw, bw, 0, c->stream, a);
-      hipLaunchKernelGGL(k_reorder_scatter<FP64>, gw, bw, 0, c->stream, a);
-    } else {
-      hipLaunchKernelGGL(k_reorder_gather<Mixed>, gw, bw, 0, c->stream, a);
-      hipLaunchKernelGGL(k_reorder_scatter<Mixed>, gw, bw, 0, c->stream, a);
-    }
+    // the reorder's scatter runs inside the list build (build_tile)
+    if (c->fp64) hipLaunchKernelGGL(k_reorder_gather<FP64>, gw, bw, 0, c->stream, a);
+    else hipLaunchKernelGGL(k_reorder_gather<Mixed>, gw, bw, 0, c->stream, a);
   }
   const int use_work = c->cell_prep ? 0 : 1;
   const dim3 gl(use_work ? round8(std::min(WORK_BLOCKS, (c->ntiles + BUILD_WAVES - 1) / BUILD_WAVES))
@@ -377,6 +373,12 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
   if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a, use_work);
   else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a, use_work);
   else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a, use_work);
+  if (use_work) {                  // small rebuild sets: the same lists with several lanes per atom
+    const dim3 gs2(round8(std::min(WORK_BLOCKS, c->ntiles))), bs2(TILE * BUILD_LPA);
+    if (c->fp64) hipLaunchKernelGGL((k_build_list_lanes<FP64, int>), gs2, bs2, 0, c->stream, a);
+    else if (c->list16) hipLaunchKernelGGL((k_build_list_lanes<Mixed, uint16_t>), gs2, bs2, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_build_list_lanes<Mixed, int>), gs2, bs2, 0, c->stream, a);
+  }
 }
 
 void launch_start(rcell_ctx* c) {
