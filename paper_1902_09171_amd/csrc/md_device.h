@@ -12,8 +12,9 @@
 //               the displacement check allows for the quantisation, see qeps)
 //   nbr         Verlet list within rc + skin, cell-local j, as 16-bit indices when every cell has
 //               at most 65536 atoms (mixed precision), else 32-bit; entries of one atom in blocks
-//               of NBLK, the blocks of entries [b NBLK, (b+1) NBLK) of all atoms side by side
-//               (list_index), so a lane loads its UNR entries of a trip with one vector load
+//               of B = 8 (Kremer-Grest) or 16 (Sutton-Chen), the blocks of entries [b B, (b+1) B) of
+//               all atoms side by side (list_index), so a lane loads its UNR entries of a trip with
+//               one vector load
 //   bond        up to four FENE partners per atom (cell-local positions; the atom's own position marks an
 //               empty slot), 16-bit slots when the list entries are 16-bit, else 32-bit
 //   gid         original cell-local index of the atom stored at each position; pos_of inverts it;
@@ -34,7 +35,8 @@ constexpr int TILE = 64;
 constexpr int BIN_BITS = 10;     // bins per dimension < 2^BIN_BITS (bin coordinates are packed)
 constexpr int BIN_MASK = (1 << BIN_BITS) - 1;
 constexpr int UNR = 4;           // neighbour-loop unroll: gathers in flight per lane
-constexpr int NBLK = 16;         // list block: consecutive entries of one atom (capacity is a multiple)
+constexpr int NBLK_MAX = 16;     // list blocks: 2^lblk consecutive entries of one atom, 8 or 16 (the
+                                 // capacity is a multiple of 16)
 constexpr double TWO32 = 4294967296.0;
 constexpr double TWOM32 = 1.0 / 4294967296.0;
 
@@ -44,11 +46,14 @@ enum Status : int { ST_OK = 0, ST_BOND = -4, ST_CAP = -8, ST_BOX = -3, ST_BAD_F 
 
 struct alignas(32) S64 { long long x, y, z, w; };
 
-// Element index of list entry k of atom i (batch position) in a list of npad atoms: blocks of NBLK
-// consecutive entries of one atom, the blocks of all atoms for entries [b NBLK, (b+1) NBLK) stored
-// together in atom order.  The list holds < 2^32 elements, so 32-bit arithmetic is exact.
-__host__ __device__ inline unsigned list_index(unsigned k, unsigned npad, unsigned i) {
-  return (k / NBLK * npad + i) * NBLK + k % NBLK;
+// Element index of list entry k of atom i (batch position) in a list of npad atoms: blocks of
+// B = 2^lb consecutive entries of one atom, the blocks of all atoms for entries [b B, (b+1) B) stored
+// together in atom order.  The list holds < 2^32 elements, so 32-bit arithmetic is exact.  Short
+// Kremer-Grest lists (~20 entries) take B = 8, so that an atom's last block wastes fewer fetched
+// bytes; Sutton-Chen lists take B = 16, so that the 16 entries its lane group reads per trip are one
+// contiguous piece.
+__host__ __device__ inline unsigned list_index(unsigned k, unsigned npad, unsigned i, int lb) {
+  return (((k >> lb) * npad + i) << lb) | (k & ((1u << lb) - 1u));
 }
 
 struct CellDev {
@@ -133,6 +138,7 @@ struct MDArgs {
   void* nbr;                       // LT entries (uint16_t or int), see the kernels' LT parameter
   long long npad;
   int maxnb;
+  int lblk;                        // list blocks of 2^lblk entries (list_index)
   CellDev* cells;
   const Tile* tiles;
   Part* parts;
@@ -655,7 +661,7 @@ struct ListVec {
     else return (int)w[u];
   }
 };
-static_assert(NBLK % UNR == 0, "a trip's entries must lie in one list block");
+static_assert(8 % UNR == 0, "a trip's entries must lie in one list block");
 
 // One lane's walk over atom i's list.  Per trip the lane takes UNR consecutive entries (one vector
 // load) and the TPA lanes of the atom take consecutive groups of UNR.  The next trip's entries are
@@ -667,11 +673,11 @@ template <class P, int TPA, class LT>
 struct NbrWalk {
   const LT* list;
   unsigned np, ii;
-  int nn, k0;
+  int nn, k0, lb;
   ListVec<LT> nx;
   __device__ NbrWalk(const MDArgs& a, long long i, int nn_, int lane)
-      : list((const LT*)a.nbr), np((unsigned)a.npad), ii((unsigned)i), nn(nn_), k0(lane * UNR), nx{} {
-    if (k0 < nn) nx.load(list + list_index((unsigned)k0, np, ii));
+      : list((const LT*)a.nbr), np((unsigned)a.npad), ii((unsigned)i), nn(nn_), k0(lane * UNR), lb(a.lblk), nx{} {
+    if (k0 < nn) nx.load(list + list_index((unsigned)k0, np, ii, lb));
   }
   __device__ bool more() const { return k0 < nn; }
   __device__ void next(const typename P::S* sc, typename P::S sj[UNR], bool ok[UNR]) {
@@ -681,7 +687,7 @@ struct NbrWalk {
       sj[u] = P::load_rel(sc, ok[u] ? nx.get(u) : 0);
     }
     k0 += UNR * TPA;
-    if (k0 < nn) nx.load(list + list_index((unsigned)k0, np, ii));
+    if (k0 < nn) nx.load(list + list_index((unsigned)k0, np, ii, lb));
   }
 };
 
@@ -1772,7 +1778,7 @@ __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int s
         typename P::R d[3];
         P::sep(sj[u], si, g, d);
         if (pos[u] != li && d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rcs2) {
-          if (count < cap) list[list_index((unsigned)count, np, ii)] = (LT)pos[u];
+          if (count < cap) list[list_index((unsigned)count, np, ii, a.lblk)] = (LT)pos[u];
           ++count;
         }
       }
@@ -1869,7 +1875,7 @@ __device__ __forceinline__ void build_tile_lanes(const MDArgs& a, const Tile& t,
         const unsigned gm = (unsigned)(__ballot(acc) >> gshift) & ((1u << BUILD_LPA) - 1u);
         if (acc) {
           const int k = count + __popc(gm & below);
-          if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii)] = (LT)pos[u];
+          if (k < a.maxnb) ((LT*)a.nbr)[list_index((unsigned)k, np, ii, a.lblk)] = (LT)pos[u];
         }
         count += __popc(gm);
       }

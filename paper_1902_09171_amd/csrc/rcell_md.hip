@@ -209,6 +209,7 @@ MDArgs make_args(const rcell_ctx* c) {
   a.bond = c->bond; a.bond0 = c->bond0; a.bond16 = c->list16 ? 1 : 0;
   a.gid = c->gid; a.pos_of = c->pos_of; a.pscr = c->pscr;
   a.nn = c->nn; a.nbr = c->nbr; a.npad = c->npad; a.maxnb = c->maxnb;
+  a.lblk = c->p.potential == RCELL_POT_KG ? 3 : 4;   // list blocks of 8 (short KG lists) or 16 entries
   a.cells = c->cells; a.tiles = c->tiles; a.parts = c->parts; a.ntiles = c->ntiles; a.ncells = c->ncells;
   a.abin = c->abin; a.bcount = c->bcount; a.bstart = c->bstart; a.bnum = c->bnum; a.bfill = c->bfill;
   a.binned = c->binned;
@@ -488,7 +489,7 @@ int layout_bins(rcell_ctx* c, const std::vector<int>& need) {
 }
 
 int ensure_list_capacity(rcell_ctx* c, int need) {
-  need = (need + NBLK - 1) / NBLK * NBLK;          // whole list blocks
+  need = (need + NBLK_MAX - 1) / NBLK_MAX * NBLK_MAX;   // whole list blocks of either length
   if (need <= c->maxnb) return RCELL_OK;
   // the pair loops address the list with 32-bit element indices
   if ((unsigned long long)need * (unsigned long long)c->npad >= (1ull << 32))
