@@ -1739,22 +1739,22 @@ __device__ __forceinline__ int2 build_range(const MDArgs& a, const CellDev& C, c
   const int beg = a.bstart[bf];
   return make_int2(beg, a.bstart[bl] + a.bnum[bl] - beg);
 }
-// SCATTER: the reorder's second half for this atom happens here (its row copied from the reorder
-// scratch to the per-atom arrays, bond partners renumbered), and the candidates are read from the
-// scratch, which holds the same reordered coordinates: no other lane reads the arrays being written,
-// and the rebuild needs one launch fewer.
-template <class P, class LT, bool SCATTER>
+// The reorder's second half for this atom happens here (its row copied from the reorder scratch to
+// the per-atom arrays, bond partners renumbered), and the candidates are read from the scratch, which
+// holds the same reordered coordinates: no other lane reads the arrays being written, and the
+// rebuild needs no separate scatter launch.
+template <class P, class LT>
 __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int slot) {
   if (slot >= t.count) return;
   const CellDev& C = a.cells[t.cell];
   const long long i = (long long)t.begin + slot;
   const int li = (int)(i - C.off);
   const Reorder<P> ro(a);
-  if constexpr (SCATTER) reorder_scatter_atom<P>(a, C, i);
-  const typename P::S* sbase = SCATTER ? (const typename P::S*)ro.s : (const typename P::S*)a.s_cur;
+  reorder_scatter_atom<P>(a, C, i);
+  const typename P::S* sbase = (const typename P::S*)ro.s;
   const typename P::S si = sbase[i];
   BuildGeo G;
-  build_geo(C, SCATTER ? ro.abin[i] : a.abin[i], a.bin_factor, G);
+  build_geo(C, ro.abin[i], a.bin_factor, G);
   const typename P::R rcs2 = (typename P::R)a.rcs2;
   const typename P::Geo g = P::geo(C);
   const typename P::S* sc = sbase + C.off;
@@ -1792,38 +1792,28 @@ __device__ __forceinline__ void build_tile(const MDArgs& a, const Tile& t, int s
   a.nn[i] = count;
 }
 
-// use_work: the tiles of the rebuild work list, one per wave, block-strided (XcdLoop), with the
-// reorder's scatter fused in; else (the one-block-per-cell preparation has done the whole reorder)
-// one wave per tile of the batch, placed like the force passes, exiting at once for cells that do
-// not rebuild
-// Rebuild sets of fewer than BUILD_SPLIT tiles leave most of the GPU idle with one lane per atom;
-// there k_build_list_lanes builds the same lists with BUILD_LPA lanes per atom (below).
+// The tiles of the rebuild work list, one per wave, block-strided (XcdLoop), with the reorder's
+// scatter fused in.  Rebuild sets of fewer than BUILD_SPLIT tiles leave most of the GPU idle with one
+// lane per atom; there k_build_list_lanes builds the same lists with BUILD_LPA lanes per atom.
 constexpr int BUILD_SPLIT = 4096;
 template <class P, class LT>
-__global__ __launch_bounds__(TILE * BUILD_WAVES) void k_build_list(MDArgs a, int use_work) {
+__global__ __launch_bounds__(TILE * BUILD_WAVES) void k_build_list(MDArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (use_work) {
-    if (a.work_count[1] < BUILD_SPLIT) return;
-    const XcdLoop L(a.work_count[1], BUILD_WAVES, wave);
-    for (int k = L.k; k < L.end; k += L.step) build_tile<P, LT, true>(a, a.tiles[work_tile(a, k)], lane);
-  } else {
-    const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
-    if (tb >= a.ntiles || wave != 0) return;
-    const Tile t = a.tiles[tb];
-    if (!a.cells[t.cell].rebuild) return;
-    build_tile<P, LT, false>(a, t, lane);
-  }
+  if (a.work_count[1] < BUILD_SPLIT) return;
+  const XcdLoop L(a.work_count[1], BUILD_WAVES, wave);
+  for (int k = L.k; k < L.end; k += L.step) build_tile<P, LT>(a, a.tiles[work_tile(a, k)], lane);
 }
 
 // The same lists for small rebuild sets, BUILD_LPA lanes per atom: the atom's ranges are looked up
 // once into LDS, its lanes walk the concatenated candidates interleaved (lane l takes candidates l,
 // l + BUILD_LPA, ...), and for each candidate slot a ballot over the atom's lanes gives every
 // accepted candidate its index (the running count plus the accepted lanes below), so the list
-// comes out in the same candidate order as with one lane per atom.  The reorder's scatter is fused
-// in as in k_build_list (the atom's first lane copies its row).
+// comes out in the same candidate order as with one lane per atom.  SCATTER: the reorder's scatter
+// is fused in as in k_build_list (the atom's first lane copies its row); without it (after the
+// one-block-per-cell preparation, which reorders completely) the candidates come from s_cur.
 constexpr int BUILD_LPA = 8;
 constexpr int MAX_RANGES = (2 * MAX_BIN_FACTOR + 1) * (2 * MAX_BIN_FACTOR + 1) * 2;
-template <class P, class LT>
+template <class P, class LT, bool SCATTER>
 __device__ __forceinline__ void build_tile_lanes(const MDArgs& a, const Tile& t, int2 (*rng)[MAX_RANGES]) {
   const int slot = threadIdx.x / BUILD_LPA, lane = threadIdx.x % BUILD_LPA;
   const bool active = slot < t.count;
@@ -1831,11 +1821,13 @@ __device__ __forceinline__ void build_tile_lanes(const MDArgs& a, const Tile& t,
   const long long i = (long long)t.begin + (active ? slot : 0);
   const int li = (int)(i - C.off);
   const Reorder<P> ro(a);
-  if (active && lane == 0) reorder_scatter_atom<P>(a, C, i);
-  const typename P::S* sc = (const typename P::S*)ro.s + C.off;
+  if constexpr (SCATTER) {
+    if (active && lane == 0) reorder_scatter_atom<P>(a, C, i);
+  }
+  const typename P::S* sc = (SCATTER ? (const typename P::S*)ro.s : (const typename P::S*)a.s_cur) + C.off;
   const typename P::S si = sc[li];
   BuildGeo G;
-  build_geo(C, ro.abin[i], a.bin_factor, G);
+  build_geo(C, SCATTER ? ro.abin[i] : a.abin[i], a.bin_factor, G);
   int2* rg = rng[slot];
   for (int r = lane; r < G.nrange; r += BUILD_LPA) rg[r] = build_range(a, C, G, r);
   __syncthreads();
@@ -1895,14 +1887,25 @@ __device__ __forceinline__ void build_tile_lanes(const MDArgs& a, const Tile& t,
   }
 }
 
+// use_work: the work list's tiles, block-strided (XcdLoop), when there are fewer than BUILD_SPLIT;
+// else one block per tile of the batch (placed like the force passes), exiting at once for cells
+// that do not rebuild
 template <class P, class LT>
-__global__ __launch_bounds__(TILE * BUILD_LPA) void k_build_list_lanes(MDArgs a) {
+__global__ __launch_bounds__(TILE * BUILD_LPA) void k_build_list_lanes(MDArgs a, int use_work) {
   __shared__ int2 rng[TILE][MAX_RANGES];      // candidate ranges (first position, count) per atom
-  if (a.work_count[1] >= BUILD_SPLIT) return;
-  const XcdLoop L(a.work_count[1]);
-  for (int k = L.k; k < L.end; k += L.step) {
-    __syncthreads();                          // the previous tile's ranges have been read
-    build_tile_lanes<P, LT>(a, a.tiles[work_tile(a, k)], rng);
+  if (use_work) {
+    if (a.work_count[1] >= BUILD_SPLIT) return;
+    const XcdLoop L(a.work_count[1]);
+    for (int k = L.k; k < L.end; k += L.step) {
+      __syncthreads();                        // the previous tile's ranges have been read
+      build_tile_lanes<P, LT, true>(a, a.tiles[work_tile(a, k)], rng);
+    }
+  } else {
+    const int tb = block_tile_xcd(a.ntiles, blockIdx.x);
+    if (tb >= a.ntiles) return;
+    const Tile t = a.tiles[tb];
+    if (!a.cells[t.cell].rebuild) return;
+    build_tile_lanes<P, LT, false>(a, t, rng);
   }
 }
 

@@ -368,18 +368,19 @@ void launch_build(rcell_ctx* c, int reduce_mode = -1) {
     else hipLaunchKernelGGL(k_reorder_gather<Mixed>, gw, bw, 0, c->stream, a);
   }
   const int use_work = c->cell_prep ? 0 : 1;
-  const dim3 gl(use_work ? round8(std::min(WORK_BLOCKS, (c->ntiles + BUILD_WAVES - 1) / BUILD_WAVES))
-                         : tile_grid(c->ntiles)),
-      bl(use_work ? TILE * BUILD_WAVES : TILE);
-  if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a, use_work);
-  else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a, use_work);
-  else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a, use_work);
-  if (use_work) {                  // small rebuild sets: the same lists with several lanes per atom
-    const dim3 gs2(round8(std::min(WORK_BLOCKS, c->ntiles))), bs2(TILE * BUILD_LPA);
-    if (c->fp64) hipLaunchKernelGGL((k_build_list_lanes<FP64, int>), gs2, bs2, 0, c->stream, a);
-    else if (c->list16) hipLaunchKernelGGL((k_build_list_lanes<Mixed, uint16_t>), gs2, bs2, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_build_list_lanes<Mixed, int>), gs2, bs2, 0, c->stream, a);
+  if (use_work) {                  // large rebuild sets: one lane per atom
+    const dim3 gl(round8(std::min(WORK_BLOCKS, (c->ntiles + BUILD_WAVES - 1) / BUILD_WAVES))), bl(TILE * BUILD_WAVES);
+    if (c->fp64) hipLaunchKernelGGL((k_build_list<FP64, int>), gl, bl, 0, c->stream, a);
+    else if (c->list16) hipLaunchKernelGGL((k_build_list<Mixed, uint16_t>), gl, bl, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_build_list<Mixed, int>), gl, bl, 0, c->stream, a);
   }
+  // small rebuild sets, and every build after the one-block-per-cell preparation: the same lists
+  // with several lanes per atom
+  const dim3 gs2(use_work ? round8(std::min(WORK_BLOCKS, c->ntiles)) : (unsigned)tile_grid(c->ntiles)),
+      bs2(TILE * BUILD_LPA);
+  if (c->fp64) hipLaunchKernelGGL((k_build_list_lanes<FP64, int>), gs2, bs2, 0, c->stream, a, use_work);
+  else if (c->list16) hipLaunchKernelGGL((k_build_list_lanes<Mixed, uint16_t>), gs2, bs2, 0, c->stream, a, use_work);
+  else hipLaunchKernelGGL((k_build_list_lanes<Mixed, int>), gs2, bs2, 0, c->stream, a, use_work);
 }
 
 void launch_start(rcell_ctx* c) {
