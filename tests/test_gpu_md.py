@@ -431,6 +431,23 @@ def test_rebuild_preparation_paths_are_bitwise_equal(rc, prec):
         g.set_build_mode(3)
 
 
+def test_one_lane_and_eight_lane_list_builds_agree(rc):
+    # a rebuild covering at least 4096 tiles takes the one-lane-per-atom list build, a smaller one the
+    # eight-lane build: the first build of 72 cells of 4100 beads at once (4680 tiles) and of the
+    # same cells in batches of 8 (520 tiles) must give the same lists, hence the same forces and
+    # stresses bit for bit (each atom sums its pairs in list order)
+    cells = kg_cells([[100] * 41] * 72, seed0=800)
+    p = configs.kg_params(precision="mixed", skin=0.7)
+    big = rc.RCellBatch(p, cells)
+    sig_big = big.get_stress()
+    for b in range(0, 72, 8):
+        small = rc.RCellBatch(p, cells[b:b + 8])
+        assert np.array_equal(small.get_stress(), sig_big[b:b + 8]), b
+        for k in range(8):
+            assert np.array_equal(small.get_forces(k), big.get_forces(b + k)), (b, k)
+    assert np.all(big.status() == 0)
+
+
 @pytest.mark.parametrize("pot", ["kg", "cu"])
 def test_graph_replay_equals_eager_launches(rc, pot):
     # replays of the captured MD-step graphs (with neighbour rebuilds inside) give bit-identical
