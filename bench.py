@@ -649,6 +649,7 @@ def bench_surrogate(args, torch, rcell, configs):
            "config": {"workload": "surrogate", "description": "MLP 153 -> 4 x 256 -> 6, ensemble of 5, "
                       "random-init weights; a step is one ensemble evaluation of the FE bar's 256 Gauss "
                       "points", "batch": B_BAR, "params_per_member": macs + 4 * WIDTH + DOUT},
+           "gpu_us_per_call_at_batch": ev_bar * 1e6,
            "evals_per_s_large_batch": B_BIG / t_big, "large_batch": B_BIG,
            "train_samples_per_s": B_TRAIN / t_trn, "train_batch": B_TRAIN,
            "roofline": roofline}
