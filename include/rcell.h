@@ -171,9 +171,10 @@ int rcell_get_rebuilds(rcell_ctx* ctx, int64_t* count);
 int rcell_set_lanes(rcell_ctx* ctx, int32_t lanes);
 /* How a neighbour rebuild prepares its cells (binning, bin order, reordering the atoms by bin):
  * mode 1 runs all of it in one launch with one block per cell (every cell must have at most 4096
- * atoms, else RCELL_ERR_ARG), mode 2 in six launches over all tiles, mode 0 (the default) picks 1
- * when every cell is small enough.  Results are identical either way; mode 1 also runs the per-cell
- * reduction of each MD step in the same launch, which makes a step six launches shorter. */
+ * atoms, else RCELL_ERR_ARG), mode 2 in six launches over the tiles of the cells that rebuild,
+ * mode 0 (the default) picks 1 when every cell is small enough.  Results are identical either way;
+ * mode 1 also runs the per-cell reduction of each MD step in the same launch, which makes a step
+ * six launches shorter. */
 int rcell_set_build_mode(rcell_ctx* ctx, int32_t mode);
 int rcell_get_lanes(rcell_ctx* ctx, int32_t* lanes);
 /* Width of the neighbour-build bins: at least (rc + skin) / f along every perpendicular box width,
