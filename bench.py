@@ -565,8 +565,11 @@ def bench_fe(args, torch, rcell, configs, name):
         bar.step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_s = []                    # each load step ends with the stress on the host (synchronised)
     for k in range(args.steps):
+        ts = time.perf_counter()
         bar.step()
+        step_s.append(time.perf_counter() - ts)
         log(f"load step {k + 1}/{args.steps}: tensile stress {bar.history[-1]['tensile']:.4f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -582,7 +585,9 @@ def bench_fe(args, torch, rcell, configs, name):
                                                  "per load step",
                    "cells": mesh.ngp, "atoms": natoms, "md_steps_per_step": MD_PER_LOAD,
                    "lanes_per_atom": lanes, "bin_factor": binf, "skin": params["skin"], "rebuilds": md.g.rebuilds()}, roofline,
-                  extra={"fe_wall_s_per_load_step": elapsed / args.steps})
+                  extra={"fe_wall_s_per_load_step": elapsed / args.steps,
+                         "load_step_ms": {"median": float(np.median(step_s)) * 1e3, "min": min(step_s) * 1e3,
+                                          "max": max(step_s) * 1e3}})
     if not args.no_cpu_baseline:
         sub = list(range(min(len(cells), host_threads())))
         F = np.stack([np.eye(3)] * len(sub))
