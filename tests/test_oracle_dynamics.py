@@ -146,6 +146,27 @@ def test_window_average_then_rotate(relaxed_kg):
     assert np.abs(P[0] @ F.T / J - unvoigt(avg[0])).max() < 1e-12 * np.abs(avg).max()
 
 
+def test_a_deformation_empties_the_window(relaxed_kg):
+    # the window holds the steps since the last get_stress or set_deformation: right after a
+    # deformation it is empty and get_stress returns the instantaneous stress of the remapped state,
+    # (W - sum m v v) / V with W from the pinned force routine, rotated by the Q of F (Eq. 7; Q from
+    # numpy's QR with R_ii > 0), not an average over the steps run before the deformation
+    p, cell = relaxed_kg
+    ob = core.OracleBatch(p, [cell])
+    ob.run(20)
+    F = np.array([[1.04, 0.03, 0.00], [-0.02, 0.98, 0.01], [0.01, 0.02, 1.02]])
+    ob.set_deformation(F[None])
+    st = ob.get_state(0)
+    _, _, W = core.forces(p, st["H"], st["x"], cell["bonds"])
+    K = p["mass"] * p["mvv2e"] * st["v"].T @ st["v"]
+    sig_md = (W - K) / abs(np.linalg.det(st["H"]))
+    Q, R = np.linalg.qr(F)
+    Q = Q * np.sign(np.diag(R))
+    expected = Q @ sig_md @ Q.T
+    got = unvoigt(ob.get_stress()[0])
+    assert np.abs(got - expected).max() < 1e-10 * np.abs(expected).max()
+
+
 def test_set_deformation_is_atomic_on_error():
     c1 = configs.kg_single()
     ob = core.OracleBatch(c1["params"], c1["cells"] * 2)

@@ -38,6 +38,21 @@ MUTANTS = [
      "c->v[3 * i + 1] = sd * r0 * cos(two_pi * u[1]);", "dynamics"),
     ("centre-of-mass velocity kept", "c->v[3 * i + q] -= mean[q];", "c->v[3 * i + q] -= 0.0 * mean[q];", "dynamics"),
     ("3N degrees of freedom", "sqrt(kt_m * (3.0 * c->n - 3.0) / sum2)", "sqrt(kt_m * (3.0 * c->n) / sum2)", "dynamics"),
+    ("window average over one step too many",
+     "sv[q] = c->wcount > 0 ? c->wsum[q] / (double)c->wcount : c->last[q];",
+     "sv[q] = c->wcount > 0 ? c->wsum[q] / (double)(c->wcount + 1) : c->last[q];", "dynamics"),
+    ("window kept across a deformation",
+     "    memset(c->wsum, 0, sizeof c->wsum); c->wcount = 0;\n    wrap_positions(c);\n    int st = prime(&C->p, c);",
+     "    wrap_positions(c);\n    int st = prime(&C->p, c);", "dynamics"),
+    ("drift before the first half kick",
+     "  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->v[k] += h * c->f[k];\n"
+     "  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->x[k] += p->dt * c->v[k];\n  wrap_positions(c);\n  double W[9];",
+     "  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->x[k] += p->dt * c->v[k];\n"
+     "  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->v[k] += h * c->f[k];\n  wrap_positions(c);\n  double W[9];",
+     "dynamics"),
+    ("J left at 1 after a deformation", "c->J = c->R[0] * c->R[4] * c->R[8];", "c->J = 1.0;", "coupling"),
+    ("positions not remapped by Delta R",
+     "for (int32_t i = 0; i < c->n; ++i) matvec(dR + 9 * k, &c->x[3 * i], &c->x[3 * i]);", "", "coupling"),
     # the cell-list branch of the pair search: bins narrower than the cutoff in a skewed box, and a
     # stencil that misses the neighbouring bin below
     ("bin count from the box edge instead of the perpendicular width",
