@@ -103,6 +103,19 @@ def test_free_particle_ornstein_uhlenbeck():
     assert c == pytest.approx(np.exp(-0.5 * k * p["dt"]), abs=0.03)
 
 
+def test_kinetic_stress_in_metal_units():
+    # a non-interacting copper cell (eps = 0) created without velocities: the velocities drawn from
+    # the seed carry exactly (3N - 3) kB T of kinetic energy twice over (Sum m v.v), so the trace of
+    # the instantaneous stress is -(3N - 3) kB T / V in eV / A^3, whatever the units of m v^2: a
+    # kinetic tensor or a draw that drops the amu A^2 / fs^2 -> eV conversion is off by ~104x
+    p = configs.cu_params(precision="fp64", sc_eps=0.0)
+    cell = dict(configs.cu_cell(3, ncell=5), v=None)
+    ob = core.OracleBatch(p, [cell])
+    s = ob.get_stress()[0]
+    n, V = len(cell["x"]), abs(np.linalg.det(np.asarray(cell["H0"], float)))
+    assert s[:3].sum() == pytest.approx(-(3 * n - 3) * configs.KB_EV * p["temperature"] / V, rel=1e-12)
+
+
 def test_noise_is_keyed_by_seed_cell_step():
     rng = np.random.default_rng(1)
     n, L = 50, 20.0

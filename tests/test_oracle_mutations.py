@@ -50,6 +50,9 @@ MUTANTS = [
      "  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->x[k] += p->dt * c->v[k];\n"
      "  for (int64_t k = 0; k < 3 * (int64_t)c->n; ++k) c->v[k] += h * c->f[k];\n  wrap_positions(c);\n  double W[9];",
      "dynamics"),
+    ("kinetic tensor without the metal-units factor",
+     "K[3 * a + b] += p->mass * p->mvv2e * c->v[3 * i + a] * c->v[3 * i + b];",
+     "K[3 * a + b] += p->mass * c->v[3 * i + a] * c->v[3 * i + b];", "dynamics"),
     ("J left at 1 after a deformation", "c->J = c->R[0] * c->R[4] * c->R[8];", "c->J = 1.0;", "coupling"),
     ("positions not remapped by Delta R",
      "for (int32_t i = 0; i < c->n; ++i) matvec(dR + 9 * k, &c->x[3 * i], &c->x[3 * i]);", "", "coupling"),
