@@ -53,6 +53,14 @@ MUTANTS = [
     ("kinetic tensor without the metal-units factor",
      "K[3 * a + b] += p->mass * p->mvv2e * c->v[3 * i + a] * c->v[3 * i + b];",
      "K[3 * a + b] += p->mass * c->v[3 * i + a] * c->v[3 * i + b];", "dynamics"),
+    ("previous stretch not updated by a deformation", "    memcpy(c->Rprev, R + 9 * k, sizeof c->Rprev);\n", "", "coupling"),
+    ("statics returns the stress of the unrelaxed start", "    if (st == OK) sample_stress(p, c, W, c->last);\n", "",
+     "statics"),
+    ("statics leaves the minimiser's velocities",
+     "    memset(c->v, 0, (size_t)n3 * sizeof(double));\n    if (st == OK) sample_stress",
+     "    if (st == OK) sample_stress", "statics"),
+    ("statics converges on the summed force", "if (fmax2 <= ftol * ftol || it >= max_iter) break;",
+     "if (F2 <= ftol * ftol * 1e6 || it >= max_iter) break;", "statics"),
     ("J left at 1 after a deformation", "c->J = c->R[0] * c->R[4] * c->R[8];", "c->J = 1.0;", "coupling"),
     ("positions not remapped by Delta R",
      "for (int32_t i = 0; i < c->n; ++i) matvec(dR + 9 * k, &c->x[3 * i], &c->x[3 * i]);", "", "coupling"),
@@ -117,14 +125,16 @@ def _run_mutant(m, tmp):
     lib = os.path.join(mdir, "libm_oracle.so")
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", csrc, "-o", lib, "-lm"])
     env = dict(os.environ, RCELL_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+    # the statics pins without their slowest case (two relaxations beyond stability, ~45 s)
+    sel = ["-k", "not beyond_stability"] if target == "statics" else []
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *sel,
                         os.path.join(ROOT, "tests", f"test_oracle_{target}.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
 
 CONTROLS = [("unmutated copy", "int orc_threads(int32_t n) {", "int orc_threads(int32_t n) {", t)
-            for t in ("forces", "coupling", "dynamics", "philox")]
+            for t in ("forces", "coupling", "dynamics", "philox", "statics")]
 
 
 def test_surrogate_pins_catch_planted_mistakes():
