@@ -61,6 +61,16 @@ MUTANTS = [
      "    if (st == OK) sample_stress", "statics"),
     ("statics converges on the summed force", "if (fmax2 <= ftol * ftol || it >= max_iter) break;",
      "if (F2 <= ftol * ftol * 1e6 || it >= max_iter) break;", "statics"),
+    ("noise mean not removed", "double xi = c24 * ((double)kk[3 * i + a] - mean[a]);",
+     "double xi = c24 * (double)kk[3 * i + a];", "dynamics"),
+    ("drag omitted", "c->f[3 * i + a] = (c->f[3 * i + a] + drag * c->v[3 * i + a]) + xi;",
+     "c->f[3 * i + a] = c->f[3 * i + a] + xi;", "dynamics"),
+    ("FENE energy and force both without R0^2",
+     "*pe += -0.5 * K * R0 * R0 * log(1.0 - t);\n      double g = K * r / (1.0 - t);",
+     "*pe += -0.5 * K * log(1.0 - t);\n      double g = K * r / (1.0 - t) / (R0 * R0);", "forces"),
+    ("embedding linear in rho (energy and force alike)",
+     "      *pe += -e * c * sqrt(rho[i]);\n      rho[i] = rho[i] > 0.0 ? -e * c / (2.0 * sqrt(rho[i])) : 0.0;",
+     "      *pe += -e * c * rho[i];\n      rho[i] = -e * c;", "forces"),
     ("J left at 1 after a deformation", "c->J = c->R[0] * c->R[4] * c->R[8];", "c->J = 1.0;", "coupling"),
     ("positions not remapped by Delta R",
      "for (int32_t i = 0; i < c->n; ++i) matvec(dR + 9 * k, &c->x[3 * i], &c->x[3 * i]);", "", "coupling"),
