@@ -96,6 +96,13 @@ SUR_MUTANTS = [
     ("SiLU derivative drops a factor", "return s * (1.0 + z * (1.0 - s))", "return s * (1.0 + z * s)"),
     ("weight gradient of the wrong layer input", "gW[l] = acts[l].T @ dz", "gW[l] = acts[l + 1].T @ dz"),
     ("Adam without bias correction", "mh = m / (1 - b1 ** t)", "mh = m"),
+    ("Adam epsilon inside the root", "return p - lr * mh / (np.sqrt(vh) + eps), m, v",
+     "return p - lr * mh / np.sqrt(vh + eps), m, v"),
+    ("bias gradient averaged instead of summed", "gb[l] = dz.sum(0)", "gb[l] = dz.mean(0)"),
+    ("loss gradient without its factor 2", "return float((d * d).mean()), 2.0 * d / d.size",
+     "return float((d * d).mean()), d / d.size"),
+    ("back-propagation through the wrong pre-activation", "dz = (dz @ Ws[l].T) * silu_grad(zs[l - 1])",
+     "dz = (dz @ Ws[l].T) * silu_grad(zs[l])"),
 ]
 
 # loads the mutated file as oracle.surrogate, then runs the surrogate pins
