@@ -276,6 +276,33 @@ def test_maxwell_boltzmann_velocities_match_the_oracle(rc, prec):
     check_stress(g.get_stress(), o.get_stress(), TOL[prec], key="s100", what=f"{prec} 50 steps from drawn velocities")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_one_and_two_atom_cells_from_the_seed(rc, prec):
+    # the smallest cells the method admits, created without velocities beside a normal cell: a single
+    # atom has no degree of freedom left once the momentum is fixed (zero velocity, and the per-cell
+    # noise, whose mean is removed, is exactly zero), a bonded dimer has three
+    p = configs.kg_params(precision=prec)
+    box = np.eye(3) * 3.5
+    one = dict(x=np.array([[0.3, 0.2, 0.1]]), v=None, bonds=np.zeros((0, 2), np.int32), H0=box)
+    dimer = dict(x=np.array([[1.0, 1.0, 1.0], [1.97, 1.0, 1.0]]), v=None, bonds=np.array([[0, 1]], np.int32), H0=box)
+    cells = [one, dimer, dict(configs.kg_cell([20] * 10, 4400), v=None)]
+    g = rc.RCellBatch(p, cells)
+    o = core.OracleBatch(dict(p, precision="fp64"), cells)
+    _, ke = g.get_energy()
+    assert ke[0] == 0.0 and np.all(g.get_state(0)["v"] == 0.0)
+    assert ke[1] == pytest.approx(0.5 * 3 * p["kB"] * p["temperature"], rel=1e-12)
+    for k in (1, 2):
+        vg, vo = g.get_state(k)["v"], o.get_state(k)["v"]
+        assert np.abs(vg - vo).max() <= 1e-12 * np.abs(vo).max()
+        check_forces(g.get_forces(k), o.get_forces(k), TOL[prec], f"{prec} small cell {k}")
+    g.get_stress(); o.get_stress()
+    g.run(50); o.run(50)
+    sg, so = g.get_stress(), o.get_stress()
+    assert np.all(g.status() == 0)
+    assert np.all(g.get_state(0)["v"] == 0.0) and np.all(sg[0] == 0.0) and np.all(so[0] == 0.0)
+    check_stress(sg[1:], so[1:], TOL[prec], key="s100", what=f"{prec} dimer and 200 beads, 50 steps")
+
+
 def test_injected_allocation_failures_leave_nothing_behind(rc, monkeypatch):
     # RCELL_FAULT_ALLOC=n makes the n-th device allocation of a context fail as if the device were
     # out of memory: create must report RCELL_ERR_OOM, free what it had allocated, and a create
