@@ -863,6 +863,10 @@ def main():
     d_steps, d_warm = DEFAULTS[args.workload]
     args.steps = d_steps if args.steps is None else args.steps
     args.warmup = d_warm if args.warmup is None else args.warmup
+    if args.steps < 1 or args.warmup < 0:
+        print(json.dumps({"error": "--steps must be at least 1 and --warmup at least 0",
+                          "steps": args.steps, "warmup": args.warmup}))
+        sys.exit(2)
 
     import torch
     from paper_1902_09171_amd import rcell

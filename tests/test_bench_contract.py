@@ -6,6 +6,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -20,6 +21,14 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert out.returncode == 2
     msg = json.loads(out.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+@pytest.mark.parametrize("flags", [["--steps", "0"], ["--warmup", "-1"]])
+def test_empty_timed_region_is_refused_with_a_message(flags):
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *flags],
+                         capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert out.returncode == 2
+    assert "--steps" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
 
 
 def test_every_workload_is_listed():
