@@ -154,6 +154,8 @@ class RCellBatch:
             H0 = _f64(c["H0"], (3, 3))
             x = _f64(c["x"], (-1, 3))
             v = None if c.get("v") is None else _f64(c["v"], (-1, 3))
+            if v is not None and v.shape != x.shape:     # the library reads natoms rows of each
+                raise ValueError(f"cell {k}: v has shape {v.shape}, x has {x.shape}")
             b = np.ascontiguousarray(np.asarray(c.get("bonds", np.zeros((0, 2))), np.int32).reshape(-1, 2))
             self._keep += [H0, x, v, b]
             inits[k].natoms = len(x)
@@ -231,7 +233,12 @@ class RCellBatch:
         return dict(x=x, v=v, H=H, Rprev=Rp, step=step.value)
 
     def set_state(self, cell, x, v, H, Rprev, step):
+        if not 0 <= cell < self.ncells:
+            raise IndexError(f"cell {cell} of {self.ncells}")
         x, v, H, Rp = _f64(x, (-1, 3)), _f64(v, (-1, 3)), _f64(H, (3, 3)), _f64(Rprev, (3, 3))
+        n = self.natoms[cell]
+        if x.shape != (n, 3) or v.shape != (n, 3):       # the library reads n rows of each
+            raise ValueError(f"cell {cell} has {n} atoms: x {x.shape}, v {v.shape}")
         self._check(load().rcell_set_state(self._h, cell, _p(x), _p(v), _p(H), _p(Rp), int(step)))
 
     def get_energy(self):

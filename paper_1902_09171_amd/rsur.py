@@ -80,7 +80,8 @@ class Surrogate:
 
     def set_params(self, member, w):
         w = _f32(w)
-        assert w.size == self.nparams
+        if w.size != self.nparams:                      # the library reads nparams floats
+            raise ValueError(f"{w.size} parameters given, the network has {self.nparams}")
         self._check(load().rsur_set_params(self._h, member, w.ctypes.data))
 
     def get_params(self, member):
@@ -95,6 +96,9 @@ class Surrogate:
 
     def set_norm(self, x_mu, x_sd, y_mu, y_sd):
         a = [_f32(v) for v in (x_mu, x_sd, y_mu, y_sd)]
+        if [v.size for v in a] != [self.din, self.din, self.dout, self.dout]:
+            raise ValueError(f"normalisation sizes {[v.size for v in a]}, expected din, din, dout, dout = "
+                             f"{[self.din, self.din, self.dout, self.dout]}")
         self._check(load().rsur_set_norm(self._h, *[v.ctypes.data for v in a]))
 
     def fit_norm(self, X_dev_ptr, Y_dev_ptr, n):

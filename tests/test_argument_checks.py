@@ -81,3 +81,27 @@ def test_surrogate_shapes(rc, shape):
     with pytest.raises(rc.RCellError) as e:
         rsur.Surrogate(**kw)
     assert e.value.code == rc.ERR_ARG and "din, dout" in str(e.value), str(e.value)
+
+
+def test_binding_checks_array_lengths_before_the_library_reads_them(rc):
+    # the library reads natoms rows of x and v: a shorter v at create, or x / v of another length
+    # in set_state, are refused by the binding before any call
+    c = configs.kg_cell([20] * 10, 6)
+    with pytest.raises(ValueError, match="v has shape"):
+        rc.RCellBatch(configs.kg_params(), [dict(c, v=np.asarray(c["v"])[:-1])])
+    b = rc.RCellBatch.__new__(rc.RCellBatch)        # a batch of one 200-atom cell, never created
+    b.ncells, b.natoms, b._h = 1, [200], None
+    with pytest.raises(ValueError, match="200 atoms"):
+        b.set_state(0, np.zeros((199, 3)), np.zeros((200, 3)), np.eye(3) * 9, np.eye(3), 0)
+    with pytest.raises(IndexError):
+        b.set_state(-1, np.zeros((200, 3)), np.zeros((200, 3)), np.eye(3) * 9, np.eye(3), 0)
+
+
+def test_surrogate_binding_checks_parameter_and_normalisation_sizes(rc):
+    from paper_1902_09171_amd import rsur
+    net = rsur.Surrogate.__new__(rsur.Surrogate)     # never created: the checks come first
+    net.din, net.dout, net.nparams, net._h = 8, 2, 100, None
+    with pytest.raises(ValueError, match="99 parameters"):
+        net.set_params(0, np.zeros(99))
+    with pytest.raises(ValueError, match="normalisation sizes"):
+        net.set_norm(np.zeros(8), np.ones(8), np.zeros(3), np.ones(2))
