@@ -7,8 +7,8 @@ steps, 9 floats each (153), so the network predicts the MD-frame stress sigma_MD
 frame-indifferent history; sigma_FEM = Q sigma_MD Q^T and P = J sigma_FEM F^-T follow (Eqs. 7-8).
 Before 17 load steps have passed the history is padded with R = I.  Targets: the window-averaged
 MD stress of each load step (6 Voigt components).  The ensemble spread flags points outside the
-training data (threshold: a high quantile of the spread on held-out data); those points take
-their stress from MD r-cells that replay their deformation history.
+training data (threshold: the largest spread met on held-out bars); those points take their
+stress from MD r-cells that replay their deformation history.
 """
 import numpy as np
 
