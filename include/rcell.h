@@ -154,8 +154,11 @@ int rcell_get_forces(rcell_ctx* ctx, int32_t cell, double* f);
 /* state of one cell: x, v natoms*3; H 9; Rprev 9; step.  Any pointer may be NULL. */
 int rcell_get_state(rcell_ctx* ctx, int32_t cell, double* x, double* v, double* H, double* Rprev,
                     int64_t* step);
-/* overwrite the state of one cell (checkpoint restore); recomputes its forces and clears its
- * window.  H must be upper triangular with w/2 >= rc + skin (else RCELL_ERR_STATE / _BOX). */
+/* overwrite the state of one cell (checkpoint restore); recomputes its conservative forces and
+ * clears its window.  The Langevin part of the last step's total force is not part of the state,
+ * so the first half kick after a restore uses the conservative force alone: two runs restored
+ * from the same state agree bit for bit, but not with the run that was never interrupted.
+ * H must be upper triangular with w/2 >= rc + skin (else RCELL_ERR_STATE / _BOX). */
 int rcell_set_state(rcell_ctx* ctx, int32_t cell, const double* x, const double* v, const double* H,
                     const double* Rprev, int64_t step);
 /* potential energy of the last force evaluation and kinetic energy 1/2 sum m v^2, ncells each */
